@@ -1,0 +1,129 @@
+"""Pins of the oracle's staggered operator (no GPU).
+
+Checks against things other than the oracle itself: the free-field spectrum
+m^2 + sum sin^2 p (closed form, with multiplicities), anti-Hermiticity of D,
+Hermiticity/positivity of A, the bound |D| <= 4, gauge covariance, and the
+exact FFT solve at U = 1.
+"""
+from math import comb
+
+import numpy as np
+import pytest
+
+from oracle import freefield as F
+from oracle import oracle as O
+from paper_1808_01829_amd.inputs import (gaussian_block, random_gauge, random_gauge_transform,
+                                         unit_gauge)
+
+BCS = [(1, 1, 1, 1), (1, 1, 1, -1)]
+
+
+def test_free_spectrum_4444_periodic_multiplicities():
+    # periodic 4^4: sin^2 p in {0, 1}, so A = m^2 + k with multiplicity 24 C(4,k)
+    m = 0.1
+    A = O.dense_operator((4, 4, 4, 4), (1, 1, 1, 1), unit_gauge((4, 4, 4, 4)), m, 0.0)
+    ev = np.sort(np.linalg.eigvalsh(A))
+    expect = np.sort(np.concatenate([np.full(24 * comb(4, k), m * m + k) for k in range(5)]))
+    assert np.abs(ev - expect).max() < 1e-12
+
+
+def test_free_spectrum_4444_antiperiodic_t():
+    # antiperiodic t: p_t = (2k+1) pi/4 gives sin^2 = 1/2: A = m^2 + 1/2 + k, mult 48 C(3,k)
+    m = 0.1
+    A = O.dense_operator((4, 4, 4, 4), (1, 1, 1, -1), unit_gauge((4, 4, 4, 4)), m, 0.0)
+    ev = np.sort(np.linalg.eigvalsh(A))
+    expect = np.sort(np.concatenate([np.full(48 * comb(3, k), m * m + 0.5 + k) for k in range(4)]))
+    assert np.abs(ev - expect).max() < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(2, 4, 6, 4), (4, 2, 2, 6)])
+@pytest.mark.parametrize("bc", BCS)
+def test_free_spectrum_anisotropic(dims, bc):
+    m = 0.3
+    A = O.dense_operator(dims, bc, unit_gauge(dims), m, 0.0)
+    ev = np.sort(np.linalg.eigvalsh(A))
+    assert np.abs(ev - F.spectrum(dims, bc, m)).max() < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 4, 2, 6)])
+@pytest.mark.parametrize("bc", BCS)
+def test_dslash_antihermitian(dims, bc):
+    # D_eo = -D_oe^dag; on extents of 2 both hops reach the same neighbour and
+    # must add up, otherwise this fails
+    U = random_gauge(dims, 0.9, 3)
+    vh = int(np.prod(dims)) // 2
+    n = 3 * vh
+    Doe = np.empty((n, n), dtype=complex)
+    Deo = np.empty((n, n), dtype=complex)
+    e = np.zeros(n, dtype=complex)
+    for k in range(n):
+        e[:] = 0
+        e[k] = 1
+        Doe[:, k] = O.dslash_half(dims, bc, U, 1, e.reshape(-1, 3)).reshape(-1)
+        Deo[:, k] = O.dslash_half(dims, bc, U, 0, e.reshape(-1, 3)).reshape(-1)
+    assert np.abs(Deo + Doe.conj().T).max() < 1e-15
+    assert np.abs(Doe).max() > 0.1
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_hermitian_positive_bounded(bc):
+    dims = (2, 4, 2, 6)
+    m = 0.1
+    A = O.dense_operator(dims, bc, random_gauge(dims, 0.8, 4), m, 0.0)
+    assert np.abs(A - A.conj().T).max() < 1e-14
+    ev = np.linalg.eigvalsh(A)
+    assert ev.min() >= m * m - 1e-12
+    assert ev.max() <= 16 + m * m + 1e-12
+
+
+def _gauge_transform_links(dims, U, g):
+    """U^g_mu(x) = g(x) U_mu(x) g(x+mu)^dag (periodic index wrap; a boundary
+    sign commutes with g)."""
+    Lx, Ly, Lz, Lt = dims
+    idx = np.arange(int(np.prod(dims)))
+    c = [idx % Lx, (idx // Lx) % Ly, (idx // (Lx * Ly)) % Lz, idx // (Lx * Ly * Lz)]
+    out = np.empty_like(U)
+    for mu in range(4):
+        cc = [a.copy() for a in c]
+        cc[mu] = (cc[mu] + 1) % dims[mu]
+        nb = cc[0] + Lx * (cc[1] + Ly * (cc[2] + Lz * cc[3]))
+        out[mu] = g @ U[mu] @ np.conj(np.swapaxes(g[nb], -1, -2))
+    return out
+
+
+def _parity_sites(dims, par):
+    idx = np.arange(int(np.prod(dims)))
+    Lx, Ly, Lz, Lt = dims
+    s = idx % Lx + (idx // Lx) % Ly + (idx // (Lx * Ly)) % Lz + idx // (Lx * Ly * Lz)
+    return idx[(s % 2) == par]
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 4, 2, 6)])
+@pytest.mark.parametrize("bc", BCS)
+def test_gauge_covariance(dims, bc):
+    U = random_gauge(dims, 0.8, 21)
+    g = random_gauge_transform(dims, 22)
+    Ug = _gauge_transform_links(dims, U, g)
+    ev = _parity_sites(dims, 0)
+    psi = gaussian_block(dims, 1, 23)[..., 0]
+    gpsi = np.einsum("sab,sb->sa", g[ev], psi)
+    lhs = O.mdagm(dims, bc, Ug, 0.2, 0.05, gpsi)
+    rhs = np.einsum("sab,sb->sa", g[ev], O.mdagm(dims, bc, U, 0.2, 0.05, psi))
+    assert np.abs(lhs - rhs).max() < 1e-13
+    # the half hop is covariant too (odd output sites)
+    od = _parity_sites(dims, 1)
+    lhs = O.dslash_half(dims, bc, Ug, 1, gpsi)
+    rhs = np.einsum("sab,sb->sa", g[od], O.dslash_half(dims, bc, U, 1, psi))
+    assert np.abs(lhs - rhs).max() < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 2, 8)])
+@pytest.mark.parametrize("bc", BCS)
+def test_free_field_fft_solve(dims, bc):
+    b = gaussian_block(dims, 2, 5)
+    for sigma in (0.0, 0.37):
+        xf = F.solve(dims, bc, 0.1, sigma, b)
+        for j in range(2):
+            x, k, tr = O.cg(dims, bc, unit_gauge(dims), 0.1, sigma, b[..., j], 1e-13)
+            assert tr < 1e-12
+            assert np.abs(x - xf[..., j]).max() <= 1e-11 * np.abs(xf[..., j]).max()
