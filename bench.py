@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the block multi-shift solve (one GPU).
+
+A step is one full bms_solve of the workload: all n_pf right-hand sides and
+all shifts of the rational approximation to a true FP64 relative residual
+<= tol. value = RHS columns solved (every shift passing) per second of wall
+time, inputs resident in HBM. Printed as one JSON line, with:
+  roofline      the dominant kernel's algorithmic GB/s (HIP events around each
+                launch on the library stream, summed over the timed steps)
+                against the 8 TB/s HBM peak
+  per_vector    the same library at n = 1 in FP64 (multi-shift CG per column)
+  cpu_baseline  the FP64 CPU oracle's multi-shift CG on a bounded sample
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RHS-solves/sec at 1e-10 residual, block vs per-vector CG; Dslash HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s):
+    """Time the oracle's multi-shift CG (one column, all shifts) per iteration
+    by differencing two bounded runs, then scale to a full solve."""
+    import numpy as np
+
+    from oracle import oracle as O
+    dims, bc, m = w["dims"], (1, 1, 1, -1), w["mass"]
+    sh = np.sort(r.beta)
+    b = np.ascontiguousarray(B[..., 0])
+    t0 = time.time()
+    O.mscg(dims, bc, U, m, sh, b, 1e-30, 1)
+    t1 = time.time() - t0
+    # per-iteration estimate from the first run, then a longer run within budget
+    n2 = max(3, min(40, int(budget_s / max(t1, 1e-3))))
+    t0 = time.time()
+    O.mscg(dims, bc, U, m, sh, b, 1e-30, n2)
+    t2 = time.time() - t0
+    per_it = max((t2 - t1) / (n2 - 1), 1e-9)
+    solve_s = per_it * per_vector_iters
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=1.0 / solve_s, unit="RHS-solves/s", cores=threads, kind="oracle",
+                sample=("oracle C FP64 multi-shift CG, 1 column x %d shifts at %s: %d vs 1 "
+                        "iterations timed (%.1f s), %.3f s/iteration, scaled to the %d "
+                        "iterations a per-vector solve of this workload takes"
+                        % (len(sh), "x".join(map(str, dims)), n2, t1 + t2, per_it,
+                           per_vector_iters)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--precision", choices=["f64", "mixed"], default=None)
+    ap.add_argument("--baseline-cols", type=int, default=2,
+                    help="columns solved one at a time (n = 1, FP64) for the per-vector rate")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1808_01829_amd import bms
+    from paper_1808_01829_amd.inputs import configs, gaussian_block, random_gauge
+
+    w = configs.WORKLOADS[args.workload]
+    r = configs.workload_coefficients(args.workload)
+    prec = args.precision or "f64"
+    dims, n, m, tol = w["dims"], w["n"], w["mass"], w["tol"]
+    log("bench: workload %s dims %s n %d shifts %d precision %s" % (args.workload, dims, n,
+                                                                     r.n_poles, prec))
+    t = time.time()
+    U = random_gauge(dims, w["eps"], 1000 * w["id"])
+    B = gaussian_block(dims, n, 1000 * w["id"] + 1)
+    log("bench: inputs generated in %.1f s" % (time.time() - t))
+    dev = torch.device("cuda:0")
+    Ud = torch.from_numpy(U).to(dev)
+    Bd = torch.from_numpy(B).to(dev)
+    ctx = bms.Context(dims, (1, 1, 1, -1))
+    ctx.set_gauge(Ud)
+    opts = bms.bms_default_opts()
+    opts.precision = bms.BMS_PREC_F64 if prec == "f64" else bms.BMS_PREC_MIXED
+    if w.get("reliable"):
+        opts.reliable_interval = w["reliable"]
+
+    X = None
+    for i in range(args.warmup):
+        X, st = ctx.solve(m, r.beta, Bd, tol=tol, max_iter=20000, opts=opts)
+        log("bench: warmup %d: %d iterations, max true residual %.2e" % (
+            i, st["iterations"], st["max_true_residual"]))
+    del X
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    solved = 0
+    iters = []
+    maxres = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        X, st = ctx.solve(m, r.beta, Bd, tol=tol, max_iter=20000, opts=opts)
+        res = np.asarray(st["true_residual"])
+        solved += int(np.sum(np.all(res <= tol, axis=0)))
+        iters.append(st["iterations"])
+        maxres = max(maxres, st["max_true_residual"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = ctx.timing_read()
+    ctx.timing(False)
+    log("bench: %d steps in %.3f s, iterations %s, max true residual %.2e" % (
+        args.steps, elapsed, iters, maxres))
+    value = solved / elapsed
+
+    kernels = {}
+    for name, (ms, nl, by) in kt.items():
+        if nl:
+            kernels[name] = dict(ms_total=ms, launches=nl, avg_us=1e3 * ms / nl,
+                                 gbs=(by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None)
+    dom = max((k for k in kernels if kernels[k]["gbs"]), key=lambda k: kernels[k]["ms_total"])
+    dk = kernels[dom]
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(dk["gbs"], 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None)
+
+    # per-vector baseline: same library, n = 1, FP64, one column at a time
+    pv_iters = []
+    t0 = time.perf_counter()
+    pvopts = bms.bms_default_opts()
+    for j in range(args.baseline_cols):
+        _, stv = ctx.solve(m, r.beta, Bd[..., j:j + 1].contiguous(), tol=tol, max_iter=50000,
+                           opts=pvopts)
+        pv_iters.append(stv["iterations"])
+    torch.cuda.synchronize()
+    pv_time = time.perf_counter() - t0
+    pv_rate = args.baseline_cols / pv_time
+    log("bench: per-vector FP64 %d columns in %.3f s, iterations %s" % (
+        args.baseline_cols, pv_time, pv_iters))
+
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_oracle_sample(U, B, w, r, int(np.mean(pv_iters)), args.cpu_seconds)
+        except Exception as e:  # the oracle is optional for the measurement
+            log("bench: cpu baseline failed: %r" % (e,))
+
+    out = dict(
+        metric=METRIC, value=round(value, 4), unit="RHS-solves/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(1e3 * elapsed / args.steps, 3),
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64" if prec == "f64" else "f32+f64",
+        data="synthetic",
+        config=dict(workload="%s: %s lattice, SU(3) U=exp(i*%g*H), staggered m=%g, n_pf=%d, "
+                             "%d poles of x^(-%g), tol %g, %s"
+                             % (args.workload, "x".join(map(str, dims)), w["eps"], m, n,
+                                r.n_poles, w["power"], tol, prec),
+                    lattice=list(dims), n_pf=n, n_shifts=r.n_poles, tol=tol, precision=prec),
+        roofline=roofline,
+        cpu_baseline=cpu,
+        per_vector=dict(value=round(pv_rate, 4), unit="RHS-solves/s", columns=args.baseline_cols,
+                        iterations=pv_iters, dtype="f64"),
+        block_over_per_vector=round(value / pv_rate, 3),
+        iterations=iters, max_true_residual=maxres,
+        dslash_gbs=kernels.get("hop", {}).get("gbs"),
+        kernels=kernels,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * bms — block multi-shift staggered solver for RHMC on MI355X (gfx950).
+ *
+ * C ABI of the hot path of de Forcrand & Keegan, "Rational Hybrid Monte Carlo
+ * with Block Solvers and Multiple Pseudofermions": applying the even-odd
+ * staggered normal operator to a block of n_pf pseudofermions, solving
+ * (A + sigma_s) X^(s) = B for all shifts of a rational approximation with the
+ * block multi-shift solver SBCGrQ (Algorithm 1), the pseudofermion action
+ * (eq. RA inside the action of Sec. II) and its link derivative (eq. force).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns BMS_OK (0) or a negative BMS_E* code.
+ *   bms_error_string() names a code; bms_last_error() gives the message of
+ *   the last failure on a context. Outputs are defined only on BMS_OK, except
+ *   where an entry point says otherwise (BMS_ENOCONV, BMS_EBREAKDOWN).
+ * Ownership: the caller owns every array. Device arrays are plain device
+ *   pointers (hipMalloc'ed or from a framework allocator), contiguous, in the
+ *   layouts below; work is ordered on the context's HIP stream. The library
+ *   owns only the opaque context and its workspace, which it allocates on
+ *   first use of a given shape and reuses. A context is not thread-safe and
+ *   serves one stream.
+ * Argument errors are detected on the host before any device work is
+ *   enqueued and return BMS_EINVAL with nothing written.
+ *
+ * Lattice and layouts
+ * -------------------
+ * dims = {Lx, Ly, Lz, Lt}, each even and >= 2; V = Lx*Ly*Lz*Lt, Vh = V/2.
+ * Site index idx = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t)&1;
+ * checkerboard index cb = idx >> 1.
+ * bc = {bx, by, bz, bt}, each +1 or -1: the factor of a link crossing the
+ *   lattice boundary in that direction (e.g. {1,1,1,-1} antiperiodic in t).
+ * Gauge field U[mu][idx][a][b], complex128 (interleaved re, im): the SU(3)
+ *   link from idx to idx + mu. Any complex 3x3 matrices are accepted.
+ * Block vector (even or odd sites) v[cb][color][rhs], complex128 for
+ *   BMS_PREC_F64 and complex64 for BMS_PREC_F32: site-major, right-hand
+ *   side fastest, Vh*3*n complex numbers.
+ * Solutions X[shift][cb][color][rhs], complex128, shifts in the caller's order.
+ * Link gradient G[mu][idx][a][b], complex128.
+ *
+ * Operator (Sec. IV names unimproved staggered fermions with even-odd
+ * preconditioning; the form is the textbook one):
+ *   (D psi)(x) = 1/2 sum_mu eta_mu(x) [ U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu) ]
+ *   eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}), boundary links carry bc[mu];
+ *   M = m + D,  A = M^dag M on even sites = m^2 - D_eo D_oe.
+ */
+#ifndef BMS_H
+#define BMS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BMS_OK 0
+#define BMS_EINVAL (-1)      /* bad argument (detected before any device work) */
+#define BMS_ENOMEM (-2)      /* device allocation failed */
+#define BMS_EHIP (-3)        /* a HIP runtime call failed */
+#define BMS_EBREAKDOWN (-4)  /* rank-deficient block (Cholesky pivot not positive) */
+#define BMS_ENOCONV (-5)     /* max_iter reached before every shift met tol */
+#define BMS_ENAN (-6)        /* non-finite value met in the iteration */
+#define BMS_ESTATE (-7)      /* call out of order (e.g. no gauge field set) */
+
+/* arithmetic precision */
+#define BMS_PREC_F64 0   /* everything in FP64 */
+#define BMS_PREC_F32 1   /* operator only: FP32 links, FP32 vectors (complex64 in/out) */
+#define BMS_PREC_MIXED 2 /* solver only: FP32 operator and block updates, FP64 small
+                            matrices, FP64 reliable updates and defect correction */
+
+#define BMS_MAX_RHS 32    /* largest block width n accepted */
+#define BMS_MAX_SHIFTS 64 /* largest number of shifts accepted */
+
+typedef struct bms_ctx bms_ctx;
+
+/* Solver options; bms_default_opts() fills the defaults listed here. */
+typedef struct bms_opts {
+  int precision;          /* BMS_PREC_F64 (default) or BMS_PREC_MIXED */
+  int reliable_interval;  /* MIXED: iterations between FP64 reliable updates (50) */
+  double freeze_tol;      /* a shift stops being updated once every column's residual
+                             estimate is below this; <= 0 means tol (default 0) */
+  int check_interval;     /* iterations between host-side convergence checks (8) */
+  int max_refine;         /* MIXED: rounds of per-shift defect correction (4) */
+  int qr_passes;          /* Cholesky-QR passes per iteration, 1 or 2 (1) */
+  int use_graph;          /* replay iteration chunks as a captured hipGraph (1) */
+} bms_opts;
+
+/* Solver statistics (filled on BMS_OK, BMS_ENOCONV and BMS_EBREAKDOWN). */
+typedef struct bms_stats {
+  int iterations;          /* block iterations of the multi-shift solve */
+  int hop_calls;           /* half-hop applications of n-wide (or wider) blocks */
+  int reliable_updates;    /* MIXED: FP64 residual replacements */
+  int refine_iterations;   /* MIXED: block iterations spent in defect correction */
+  int converged;           /* 1 if every shift and column met tol (true FP64 residual) */
+  double max_true_residual;/* max over shifts and columns of |b - (A+s)x| / |b| */
+  double* true_residual;   /* optional caller array [n_shifts][n]; NULL to skip */
+} bms_stats;
+
+void bms_default_opts(bms_opts* opts);
+
+/* Name of a status code (static string). */
+const char* bms_error_string(int status);
+
+/* Message of the last failure on ctx (empty if none; valid until the next call). */
+const char* bms_last_error(const bms_ctx* ctx);
+
+/*
+ * Create a context for one lattice. dims and bc as above; stream is a
+ * hipStream_t (NULL = the default stream). Performs no device work; device
+ * memory is allocated by bms_set_gauge and the first call of each shape.
+ * Errors: BMS_EINVAL for a null ctx, odd or < 2 extents, bc not +-1, or a
+ * volume above 2^28 sites.
+ */
+int bms_create(bms_ctx** ctx, const int dims[4], const int bc[4], void* stream);
+
+/* Release the context and all device memory it owns (waits for its stream). */
+int bms_destroy(bms_ctx* ctx);
+
+/*
+ * Load the gauge field (device pointer, U[mu][idx][a][b] complex128). The
+ * library keeps its own copies: per output parity, the 8 links each site's
+ * half hop needs, with the 1/2, eta_mu and boundary factors folded in (and
+ * the backward links daggered), in FP64 and FP32. U is not referenced after
+ * the call returns (the copy is ordered on the stream).
+ */
+int bms_set_gauge(bms_ctx* ctx, const void* U);
+
+/*
+ * out = D_{parity_out, 1-parity_out} in: the half hop from sites of parity
+ * 1-parity_out to sites of parity parity_out (parity_out = 1 gives D_oe,
+ * 0 gives D_eo) on n columns. precision BMS_PREC_F64 or BMS_PREC_F32 selects
+ * complex128 or complex64 arrays and arithmetic. in and out must not alias.
+ */
+int bms_apply_hop(bms_ctx* ctx, int parity_out, int n, const void* in, void* out, int precision);
+
+/*
+ * out = (A + sigma) in = (m^2 + sigma) in - D_eo D_oe in on even sites for n
+ * columns (mass = m). precision as for bms_apply_hop. in and out must not alias.
+ */
+int bms_apply_mdagm(bms_ctx* ctx, double mass, double sigma, int n, const void* in, void* out,
+                    int precision);
+
+/*
+ * Block multi-shift solve (Algorithm 1, SBCGrQ): X^(s) = (A + shifts[s])^-1 B
+ * for s = 0..n_shifts-1 and all n columns of B at once.
+ *   shifts: host array, each >= 0, any order; the smallest one drives the
+ *           unshifted recurrence (sigma_0). Duplicates are allowed.
+ *   tol:    target relative residual per column and shift, > 0. The loop runs
+ *           until every shifted residual estimate |delta^(s) e_i| / |b_i| is
+ *           below tol; then the true FP64 residuals are computed and, in MIXED
+ *           precision, shifts above tol are refined by defect correction.
+ *   B:      device block [cb][color][rhs] complex128 (even sites), full column rank.
+ *   X:      device output [shift][cb][color][rhs] complex128.
+ *   opts:   NULL for defaults. stats: NULL or caller struct.
+ * Returns BMS_OK when every column of every shift has true relative residual
+ * <= tol; BMS_ENOCONV when max_iter block iterations were not enough (X holds
+ * the last iterate, stats the residuals); BMS_EBREAKDOWN when the block lost
+ * rank (e.g. linearly dependent columns in B); BMS_ENAN on non-finite values.
+ */
+int bms_solve(bms_ctx* ctx, double mass, int n, int n_shifts, const double* shifts, double tol,
+              int max_iter, const bms_opts* opts, const void* B, void* X, bms_stats* stats);
+
+/*
+ * Pseudofermion action per column (Sec. II with eq. RA):
+ *   S_i = Re phi_i^dag (a0 phi_i + sum_j alpha[j] X^(j) phi-column i),
+ * from B (device, complex128 [cb][color][rhs]) and solutions X (device,
+ * [shift][cb][color][rhs]). S is a host array of n doubles. Blocks until done.
+ */
+int bms_action(bms_ctx* ctx, int n, int n_shifts, double a0, const double* alpha, const void* B,
+               const void* X, double* S);
+
+#define BMS_FORCE_RAW 0 /* G = dS/dRe U + i dS/dIm U, [mu][idx][3][3] complex128 */
+#define BMS_FORCE_LIE 1 /* F^a = -dS/d omega^a for U -> exp(i omega^a T^a) U, T^a = lambda_a/2,
+                           [mu][idx][8] float64 */
+
+/*
+ * Link derivative of S = sum_i sum_j alpha[j] phi_i^dag (A + s_j)^-1 phi_i
+ * (eq. force) from the solutions X^(j) = (A + s_j)^-1 B (device,
+ * [shift][cb][color][rhs] complex128) and host residues alpha[n_shifts]:
+ *   dS = -2 sum_ij alpha_j Re[ y_ij^dag dD_oe x_ij ],  y = D_oe x,
+ * i.e. per link M_mu(w) = -eta b sum alpha x(w+mu) y(w)^dag (w odd) or
+ * +eta b sum alpha y(w+mu) x(w)^dag (w even), returned as G = M^dag
+ * (flags = BMS_FORCE_RAW) or F^a = Im Tr[T^a U M] (BMS_FORCE_LIE).
+ * out is a device array overwritten in full.
+ */
+int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void* X, void* out,
+              int flags);
+
+/*
+ * Per-kernel GPU timing. While enabled, bms_solve records HIP events on the
+ * library stream around every kernel of each block iteration and accumulates,
+ * per kernel class, the summed event time, the number of launches that did
+ * work, and their algorithmic HBM bytes (each block vector, link and solution
+ * read or written once per launch; small n x n data not counted):
+ *   BMS_KERNEL_HOP      half hop, links + in + out (+ aux for the D_eo hop)
+ *   BMS_KERNEL_GRAM     P^H W Gram: 2 blocks read
+ *   BMS_KERNEL_CHOLQR   Cholesky-QR Gram: Q, W read
+ *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per active
+ *                       shift P^(s), X^(s) read and written
+ *   BMS_KERNEL_SMALL    the n x n kernels (no block data)
+ * Timing disables graph replay. bms_timing_enable(ctx, 1) also clears the
+ * accumulators; bms_timing_read returns them (host pointers, any may be NULL).
+ */
+#define BMS_KERNEL_HOP 0
+#define BMS_KERNEL_GRAM 1
+#define BMS_KERNEL_CHOLQR 2
+#define BMS_KERNEL_UPDATE 3
+#define BMS_KERNEL_SMALL 4
+#define BMS_NKERNELS 5
+
+int bms_timing_enable(bms_ctx* ctx, int enable);
+int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,
+                    double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMS_H */

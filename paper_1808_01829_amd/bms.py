@@ -1,0 +1,298 @@
+"""Thin Python binding of the bms C ABI (include/bms.h).
+
+Argument marshalling only: every step runs in libbms.so. Functions carry the
+C names; tensors are torch CUDA tensors (complex128 unless noted), contiguous,
+in the layouts of bms.h:
+
+  gauge U[mu][idx][3][3], block B[cb][3][n], solutions X[shift][cb][3][n],
+  gradient G[mu][idx][3][3] (or F[mu][idx][8] float64 for BMS_FORCE_LIE).
+
+Raises BmsError (a RuntimeError) on any non-zero status. The library must be
+built (paper_1808_01829_amd/build.py); importing fails loudly otherwise.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbms.so")
+
+BMS_OK = 0
+BMS_EINVAL = -1
+BMS_ENOMEM = -2
+BMS_EHIP = -3
+BMS_EBREAKDOWN = -4
+BMS_ENOCONV = -5
+BMS_ENAN = -6
+BMS_ESTATE = -7
+BMS_PREC_F64 = 0
+BMS_PREC_F32 = 1
+BMS_PREC_MIXED = 2
+BMS_MAX_RHS = 32
+BMS_MAX_SHIFTS = 64
+BMS_FORCE_RAW = 0
+BMS_FORCE_LIE = 1
+
+BMS_KERNEL_HOP = 0
+BMS_KERNEL_GRAM = 1
+BMS_KERNEL_CHOLQR = 2
+BMS_KERNEL_UPDATE = 3
+BMS_KERNEL_SMALL = 4
+KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small"]
+
+EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create", "bms_destroy",
+           "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",
+           "bms_force", "bms_timing_enable", "bms_timing_read"]
+
+
+class bms_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("reliable_interval", ctypes.c_int),
+                ("freeze_tol", ctypes.c_double), ("check_interval", ctypes.c_int),
+                ("max_refine", ctypes.c_int), ("qr_passes", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
+
+
+class bms_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("hop_calls", ctypes.c_int),
+                ("reliable_updates", ctypes.c_int), ("refine_iterations", ctypes.c_int),
+                ("converged", ctypes.c_int), ("max_true_residual", ctypes.c_double),
+                ("true_residual", ctypes.POINTER(ctypes.c_double))]
+
+
+class BmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_lib().bms_error_string(code).decode(), msg))
+        self.code = code
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbms.so is not built (run paper_1808_01829_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ip, dp, i, d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(
+            ctypes.c_double), ctypes.c_int, ctypes.c_double
+        L.bms_default_opts.argtypes = [ctypes.POINTER(bms_opts)]
+        L.bms_default_opts.restype = None
+        L.bms_error_string.argtypes = [i]
+        L.bms_error_string.restype = ctypes.c_char_p
+        L.bms_last_error.argtypes = [vp]
+        L.bms_last_error.restype = ctypes.c_char_p
+        L.bms_create.argtypes = [ctypes.POINTER(vp), ip, ip, vp]
+        L.bms_destroy.argtypes = [vp]
+        L.bms_set_gauge.argtypes = [vp, vp]
+        L.bms_apply_hop.argtypes = [vp, i, i, vp, vp, i]
+        L.bms_apply_mdagm.argtypes = [vp, d, d, i, vp, vp, i]
+        L.bms_solve.argtypes = [vp, d, i, i, dp, d, i, ctypes.POINTER(bms_opts), vp, vp,
+                                ctypes.POINTER(bms_stats)]
+        L.bms_action.argtypes = [vp, i, i, d, dp, vp, vp, dp]
+        L.bms_force.argtypes = [vp, i, i, dp, vp, vp, i]
+        L.bms_timing_enable.argtypes = [vp, i]
+        L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
+        for f in EXPORTS:
+            if f not in ("bms_default_opts", "bms_error_string", "bms_last_error"):
+                getattr(L, f).restype = ctypes.c_int
+        _L = L
+    return _L
+
+
+def lib():
+    """The loaded libbms.so (ctypes.CDLL)."""
+    return _lib()
+
+
+def _check(ctx, rc):
+    if rc != 0:
+        msg = _lib().bms_last_error(ctx).decode() if ctx else ""
+        raise BmsError(rc, msg)
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA tensor, or an int address."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _doubles(vals):
+    vals = [float(v) for v in vals]
+    return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+def bms_default_opts():
+    o = bms_opts()
+    _lib().bms_default_opts(ctypes.byref(o))
+    return o
+
+
+def bms_error_string(code):
+    return _lib().bms_error_string(int(code)).decode()
+
+
+def bms_create(dims, bc=(1, 1, 1, -1), stream=None):
+    """Returns an opaque context handle (ctypes.c_void_p)."""
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int * 4)(*[int(x) for x in dims])
+    b = (ctypes.c_int * 4)(*[int(x) for x in bc])
+    if stream is None:
+        stream = 0
+    rc = _lib().bms_create(ctypes.byref(h), d, b, ctypes.c_void_p(int(stream)))
+    _check(None, rc)
+    return h
+
+
+def bms_destroy(ctx):
+    _check(None, _lib().bms_destroy(ctx))
+
+
+def bms_set_gauge(ctx, U):
+    _check(ctx, _lib().bms_set_gauge(ctx, _ptr(U)))
+
+
+def bms_apply_hop(ctx, parity_out, n, inp, out, precision=BMS_PREC_F64):
+    _check(ctx, _lib().bms_apply_hop(ctx, int(parity_out), int(n), _ptr(inp), _ptr(out),
+                                     int(precision)))
+
+
+def bms_apply_mdagm(ctx, mass, sigma, n, inp, out, precision=BMS_PREC_F64):
+    _check(ctx, _lib().bms_apply_mdagm(ctx, float(mass), float(sigma), int(n), _ptr(inp),
+                                       _ptr(out), int(precision)))
+
+
+def bms_solve(ctx, mass, n, shifts, tol, max_iter, opts, B, X, want_residuals=True,
+              raise_on_error=True):
+    """Returns (status, stats dict). X is written in place."""
+    ns = len(shifts)
+    st = bms_stats()
+    res = (ctypes.c_double * (ns * n))() if want_residuals else None
+    if res is not None:
+        st.true_residual = ctypes.cast(res, ctypes.POINTER(ctypes.c_double))
+    rc = _lib().bms_solve(ctx, float(mass), int(n), ns, _doubles(shifts), float(tol),
+                          int(max_iter), ctypes.byref(opts) if opts is not None else None,
+                          _ptr(B), _ptr(X), ctypes.byref(st))
+    stats = dict(iterations=st.iterations, hop_calls=st.hop_calls,
+                 reliable_updates=st.reliable_updates, refine_iterations=st.refine_iterations,
+                 converged=bool(st.converged), max_true_residual=st.max_true_residual, status=rc)
+    if res is not None:
+        stats["true_residual"] = [[res[s * n + i] for i in range(n)] for s in range(ns)]
+    if raise_on_error:
+        _check(ctx, rc)
+    return rc, stats
+
+
+def bms_action(ctx, n, a0, alpha, B, X):
+    S = (ctypes.c_double * n)()
+    ns = len(alpha)
+    _check(ctx, _lib().bms_action(ctx, int(n), ns, float(a0), _doubles(alpha), _ptr(B), _ptr(X),
+                                  S))
+    return [S[i] for i in range(n)]
+
+
+def bms_force(ctx, n, alpha, X, out, flags=BMS_FORCE_RAW):
+    _check(ctx, _lib().bms_force(ctx, int(n), len(alpha), _doubles(alpha), _ptr(X), _ptr(out),
+                                 int(flags)))
+
+
+def bms_timing_enable(ctx, enable=True):
+    _check(ctx, _lib().bms_timing_enable(ctx, 1 if enable else 0))
+
+
+def bms_timing_read(ctx, kernel):
+    """Returns (milliseconds, launches, algorithmic bytes) accumulated for a kernel class."""
+    ms, nl, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    _check(ctx, _lib().bms_timing_read(ctx, int(kernel), ctypes.byref(ms), ctypes.byref(nl),
+                                       ctypes.byref(by)))
+    return ms.value, nl.value, by.value
+
+
+class Context:
+    """Owns a bms_ctx; torch-tensor convenience wrappers over the C calls."""
+
+    def __init__(self, dims, bc=(1, 1, 1, -1), stream=None):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        self.bc = tuple(int(b) for b in bc)
+        self.vol = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.vh = self.vol // 2
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.h = bms_create(self.dims, self.bc, stream)
+
+    def close(self):
+        if self.h is not None:
+            bms_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_gauge(self, U):
+        import torch
+        assert U.dtype == torch.complex128 and tuple(U.shape) == (4, self.vol, 3, 3)
+        bms_set_gauge(self.h, U)
+
+    def _block(self, v, dtype):
+        assert v.dtype == dtype and v.dim() == 3 and v.shape[0] == self.vh and v.shape[1] == 3, \
+            "block must be [Vh][3][n] of %s" % dtype
+        return v.shape[2]
+
+    def apply_hop(self, parity_out, v, precision=BMS_PREC_F64):
+        import torch
+        dt = torch.complex128 if precision == BMS_PREC_F64 else torch.complex64
+        n = self._block(v, dt)
+        out = torch.empty_like(v)
+        bms_apply_hop(self.h, parity_out, n, v, out, precision)
+        return out
+
+    def apply_mdagm(self, mass, sigma, v, precision=BMS_PREC_F64):
+        import torch
+        dt = torch.complex128 if precision == BMS_PREC_F64 else torch.complex64
+        n = self._block(v, dt)
+        out = torch.empty_like(v)
+        bms_apply_mdagm(self.h, mass, sigma, n, v, out, precision)
+        return out
+
+    def solve(self, mass, shifts, B, tol=1e-10, max_iter=10000, opts=None, raise_on_error=True,
+              **kw):
+        import torch
+        n = self._block(B, torch.complex128)
+        if opts is None:
+            opts = bms_default_opts()
+        for k, v in kw.items():
+            setattr(opts, k, v)
+        X = torch.empty((len(shifts),) + tuple(B.shape), dtype=torch.complex128, device=B.device)
+        rc, stats = bms_solve(self.h, mass, n, list(shifts), tol, max_iter, opts, B, X,
+                              raise_on_error=raise_on_error)
+        return X, stats
+
+    def action(self, a0, alpha, B, X):
+        n = B.shape[2]
+        return bms_action(self.h, n, a0, list(alpha), B, X)
+
+    def timing(self, enable=True):
+        bms_timing_enable(self.h, enable)
+
+    def timing_read(self):
+        return {KERNEL_NAMES[k]: bms_timing_read(self.h, k) for k in range(len(KERNEL_NAMES))}
+
+    def force(self, alpha, X, flags=BMS_FORCE_RAW):
+        import torch
+        n = X.shape[3]
+        if flags == BMS_FORCE_RAW:
+            out = torch.empty((4, self.vol, 3, 3), dtype=torch.complex128, device=X.device)
+        else:
+            out = torch.empty((4, self.vol, 8), dtype=torch.float64, device=X.device)
+        bms_force(self.h, n, list(alpha), X, out, flags)
+        return out

@@ -1,0 +1,132 @@
+// Gauge import and the multi-RHS staggered half hop (the block Dirac operator
+// of Sec. III-IV: one application serves all n pseudofermion columns).
+#include "internal.h"
+
+namespace {
+
+struct Bc {
+  int b[4];
+};
+
+// U[mu][idx][a][b] complex128 -> per output parity p and cb site s the 8 links
+//   k = mu     :  +1/2 eta_mu(x) bf U_mu(x)              (hop to x+mu)
+//   k = 4 + mu :  -1/2 eta_mu(x) bb U_mu(x-mu)^dag       (hop to x-mu)
+// bf / bb = bc[mu] if that hop crosses the boundary. FP64 and FP32 copies.
+__global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restrict__ U,
+                                                         double2* __restrict__ l64,
+                                                         float2* __restrict__ l32, Geom g, Bc bc,
+                                                         int sbl, int nblk, int vol) {
+  uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
+  if (tid >= 2u * (uint32_t)g.vh) return;
+  int par = tid >= (uint32_t)g.vh;
+  uint32_t s = tid - (par ? g.vh : 0);
+  SiteCoord c = site_coords(s, g, par);
+  int co[4] = {c.x, c.y, c.z, c.t};
+  size_t pbase = (size_t)par * nblk * 72 << sbl;
+  auto lex = [&](const int* q) { return q[0] + g.L[0] * (q[1] + g.L[1] * (q[2] + g.L[2] * q[3])); };
+  int idx = lex(co);
+  for (int mu = 0; mu < 4; ++mu) {
+    int esum = 0;
+    for (int nu = 0; nu < mu; ++nu) esum += co[nu];
+    double eta = (esum & 1) ? -0.5 : 0.5;
+    // forward
+    double ff = eta * ((co[mu] == g.L[mu] - 1) ? bc.b[mu] : 1);
+    const double2* uf = U + ((size_t)mu * vol + idx) * 9;
+    for (int e = 0; e < 9; ++e) {
+      double2 v = cscale(uf[e], ff);
+      size_t o = pbase + link_off(s, mu, e, sbl);
+      l64[o] = v;
+      l32[o] = make_float2((float)v.x, (float)v.y);
+    }
+    // backward: daggered link of the neighbour x - mu
+    int nb[4] = {co[0], co[1], co[2], co[3]};
+    nb[mu] = co[mu] == 0 ? g.L[mu] - 1 : co[mu] - 1;
+    double fb = -eta * ((co[mu] == 0) ? bc.b[mu] : 1);
+    const double2* ub = U + ((size_t)mu * vol + lex(nb)) * 9;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double2 v = cscale(cconj(ub[3 * b + a]), fb);
+        size_t o = pbase + link_off(s, 4 + mu, 3 * a + b, sbl);
+        l64[o] = v;
+        l32[o] = make_float2((float)v.x, (float)v.y);
+      }
+  }
+}
+
+// out(s) = b * sum_k L_k(s) in(nbr_k(s)) + a * aux(s), per column j.
+// One thread per (site, column): lanes of one site share its links (the
+// block operator reads each link once per n columns) and read the n columns
+// of a neighbour as one contiguous run.
+template <typename T>
+__global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ links,
+                                                const cplx<T>* __restrict__ in,
+                                                cplx<T>* __restrict__ out,
+                                                const cplx<T>* __restrict__ aux, T a, T b, Geom g,
+                                                int n, FastDiv dn, int par, int sbl,
+                                                const int* __restrict__ skip) {
+  using C = cplx<T>;
+  if (skip && *skip) return;
+  uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
+  if (tid >= (uint32_t)g.vh * (uint32_t)n) return;
+  uint32_t s = fdiv(tid, dn);
+  int j = (int)(tid - s * (uint32_t)n);
+  SiteCoord c = site_coords(s, g, par);
+  C acc0 = czero<C>(), acc1 = czero<C>(), acc2 = czero<C>();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int mu = k & 3;
+    int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
+    const C* src = in + (size_t)nb * 3 * n + j;
+    C v0 = src[0], v1 = src[n], v2 = src[2 * n];
+    const C* L = links + link_off(s, k, 0, sbl);
+    const size_t st = (size_t)1 << sbl;
+    acc0 = cfma(L[0 * st], v0, acc0);
+    acc0 = cfma(L[1 * st], v1, acc0);
+    acc0 = cfma(L[2 * st], v2, acc0);
+    acc1 = cfma(L[3 * st], v0, acc1);
+    acc1 = cfma(L[4 * st], v1, acc1);
+    acc1 = cfma(L[5 * st], v2, acc1);
+    acc2 = cfma(L[6 * st], v0, acc2);
+    acc2 = cfma(L[7 * st], v1, acc2);
+    acc2 = cfma(L[8 * st], v2, acc2);
+  }
+  size_t o = (size_t)s * 3 * n + j;
+  if (aux) {
+    out[o] = cadd(cscale(aux[o], a), cscale(acc0, b));
+    out[o + n] = cadd(cscale(aux[o + n], a), cscale(acc1, b));
+    out[o + 2 * n] = cadd(cscale(aux[o + 2 * n], a), cscale(acc2, b));
+  } else {
+    out[o] = cscale(acc0, b);
+    out[o + n] = cscale(acc1, b);
+    out[o + 2 * n] = cscale(acc2, b);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32) {
+  Bc bc;
+  for (int i = 0; i < 4; ++i) bc.b[i] = c->bc[i];
+  uint32_t nthr = 2u * c->vh;
+  k_gauge_import<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(
+      (const double2*)U, (double2*)l64, (float2*)l32, c->geom, bc, c->sbl, c->nblk, (int)c->vol);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
+                      double a, double b, const int* skip) {
+  const DevBuf& lb = sizeof(T) == 8 ? c->links64 : c->links32;
+  size_t pstride = (size_t)c->nblk * 72 << c->sbl;
+  const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
+  uint32_t nthr = (uint32_t)c->vh * (uint32_t)n;
+  k_hop<T><<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(
+      links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom, n,
+      make_fastdiv(n), par, c->sbl, skip);
+  return hipGetLastError();
+}
+
+template hipError_t launch_hop<float>(const bms_ctx*, int, int, const void*, void*, const void*,
+                                      double, double, const int*);
+template hipError_t launch_hop<double>(const bms_ctx*, int, int, const void*, void*, const void*,
+                                       double, double, const int*);

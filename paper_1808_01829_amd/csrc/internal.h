@@ -1,0 +1,93 @@
+// Internal declarations of the bms library: context, workspace, launchers.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/bms.h"
+#include "common.h"
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Device-side solver control block (all written by kernels, read by the host
+// between graph chunks).
+struct SolverFlags {
+  int stop;       // iteration over: converged, max_iter or error (skip flag)
+  int halted;     // the update kernel skips too (set one step after stop)
+  int error;      // 0 or a BMS_E* code raised on the device
+  int iter;       // completed block iterations
+  int active[BMS_MAX_SHIFTS];  // shift still updated
+  int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
+  double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift
+};
+
+struct bms_ctx {
+  int dims[4];
+  int bc[4];
+  long vol;
+  int vh;
+  Geom geom;
+  int sbl = 5;  // log2 of the link block (sites per SoA block)
+  int nblk;     // link blocks per parity
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;  // library-owned work stream
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int device = -1;
+  bool gauge_set = false;
+  DevBuf links64, links32;  // [parity][blocked links] complex
+  std::vector<DevBuf> scratch;  // named by slot index
+  std::string last_error;
+  // per-kernel timing (bms_timing_enable)
+  bool timing = false;
+  double kt_ms[BMS_NKERNELS] = {0};
+  long long kt_launches[BMS_NKERNELS] = {0};
+  double kt_bytes[BMS_NKERNELS] = {0};
+  std::vector<hipEvent_t> evpool;
+  // graph cache for the iteration chunk
+  hipGraphExec_t graph_exec = nullptr;
+  std::string graph_key;
+};
+
+// error helpers
+int set_err(bms_ctx* c, int code, const char* fmt, ...);
+#define HIP_TRY(ctx, call)                                                          \
+  do {                                                                              \
+    hipError_t _e = (call);                                                         \
+    if (_e != hipSuccess)                                                           \
+      return set_err((ctx), _e == hipErrorOutOfMemory ? BMS_ENOMEM : BMS_EHIP,      \
+                     "%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, \
+                     __LINE__);                                                     \
+  } while (0)
+
+int ensure_device(bms_ctx* c);
+int ensure_buf(bms_ctx* c, DevBuf& b, size_t bytes);
+int scratch_buf(bms_ctx* c, int slot, size_t bytes, void** p);
+int stream_begin(bms_ctx* c);
+int stream_end(bms_ctx* c);
+
+// ---- launchers (all enqueue on c->stream) ---------------------------------
+hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32);
+
+// out = b * D_{par} in  (+ a * aux if aux)  on n columns; done = optional
+// device flag (skip if *done)
+template <typename T>
+hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
+                      double a, double b, const int* skip);
+
+// Gram partials with last-block reduction: G (n x n, FP64) = X^H Y over
+// `rows` rows of n complex. partials must hold nb*n*n double2, counter one
+// int (zero on entry, left zero).
+template <typename T>
+hipError_t launch_gram(hipStream_t st, int rows, int n, const void* X, const void* Y, double2* G,
+                       double2* partials, int* counter, int nb, const int* skip);
+int gram_blocks(int rows, int n);
+
+// Y = X M (rows x n times n x n, M FP64 on device), optionally Y += (accum)
+template <typename T>
+hipError_t launch_block_matmul(hipStream_t st, int rows, int n, const void* X, const double2* M,
+                               void* Y);
+
+hipError_t launch_fill_zero(hipStream_t st, void* p, size_t bytes);

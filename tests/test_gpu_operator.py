@@ -1,0 +1,99 @@
+"""Parity of the HIP half hop and normal operator with the FP64 oracle.
+
+FP64 kernels must agree to rounding (1e-13 relative to the largest entry);
+FP32 kernels to 2e-6 (FP32 rounding of links and vectors over 8 hops)."""
+import numpy as np
+import pytest
+
+from gpu_common import rel, to_dev, to_np, torch_gpu
+from oracle import freefield as F
+from oracle import oracle as O
+from paper_1808_01829_amd.inputs import gaussian_block, random_gauge, unit_gauge
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((2, 2, 2, 2), 1), ((4, 4, 4, 4), 1), ((4, 4, 4, 4), 16), ((4, 6, 2, 8), 3),
+         ((8, 8, 8, 8), 4), ((2, 4, 6, 4), 5), ((8, 4, 4, 6), 8), ((4, 4, 4, 4), 32)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_gpu()
+
+
+def _ctx(dims, bc, U):
+    from paper_1808_01829_amd import bms
+    torch = torch_gpu()
+    c = bms.Context(dims, bc)
+    c.set_gauge(to_dev(torch, U))
+    return c
+
+
+@pytest.mark.parametrize("dims,n", CASES)
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (1, 1, 1, -1)])
+def test_hop_f64_and_f32(torch, dims, n, bc):
+    from paper_1808_01829_amd import bms
+    U = random_gauge(dims, 0.7, 101)
+    c = _ctx(dims, bc, U)
+    v = gaussian_block(dims, n, 102)
+    for par in (0, 1):
+        ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], axis=-1)
+        out = to_np(c.apply_hop(par, to_dev(torch, v)))
+        assert rel(out, ref) < 1e-13
+        out32 = to_np(c.apply_hop(par, to_dev(torch, v.astype(np.complex64)), bms.BMS_PREC_F32))
+        assert rel(out32, ref) < 2e-6
+
+
+@pytest.mark.parametrize("dims,n", CASES[:6])
+def test_mdagm_f64_and_f32(torch, dims, n):
+    from paper_1808_01829_amd import bms
+    bc = (1, 1, 1, -1)
+    U = random_gauge(dims, 0.9, 103)
+    c = _ctx(dims, bc, U)
+    v = gaussian_block(dims, n, 104)
+    for sigma in (0.0, 0.75):
+        ref = O.mdagm(dims, bc, U, 0.05, sigma, v)
+        out = to_np(c.apply_mdagm(0.05, sigma, to_dev(torch, v)))
+        assert rel(out, ref) < 1e-13
+        out32 = to_np(c.apply_mdagm(0.05, sigma, to_dev(torch, v.astype(np.complex64)),
+                                    bms.BMS_PREC_F32))
+        assert rel(out32, ref) < 5e-6
+
+
+def test_mdagm_full_size_sampled(torch):
+    # 32^4 at n = 16 (the largest workload): columns 0 and 11 against the oracle
+    dims, n, bc = (32, 32, 32, 32), 16, (1, 1, 1, -1)
+    U = random_gauge(dims, 0.8, 5000)
+    c = _ctx(dims, bc, U)
+    v = gaussian_block(dims, n, 5001)
+    out = to_np(c.apply_mdagm(0.01, 0.0, to_dev(torch, v)))
+    for j in (0, 11):
+        ref = O.mdagm(dims, bc, U, 0.01, 0.0, v[..., j])
+        assert rel(out[..., j], ref) < 1e-13
+
+
+def test_free_field_inverse_property(torch):
+    # at U = 1, (A + s) applied to the exact FFT solution returns the source
+    dims, n, bc = (16, 16, 16, 16), 4, (1, 1, 1, -1)
+    c = _ctx(dims, bc, unit_gauge(dims))
+    b = gaussian_block(dims, n, 7)
+    x = F.solve(dims, bc, 0.02, 0.1, b)
+    out = to_np(c.apply_mdagm(0.02, 0.1, to_dev(torch, x)))
+    assert rel(out, b) < 1e-12
+
+
+def test_errors(torch):
+    from paper_1808_01829_amd import bms
+    dims = (4, 4, 4, 4)
+    c = bms.Context(dims)
+    v = to_dev(torch, gaussian_block(dims, 2, 1))
+    with pytest.raises(bms.BmsError) as e:
+        c.apply_mdagm(0.1, 0.0, v)  # no gauge field yet
+    assert e.value.code == bms.BMS_ESTATE
+    c.set_gauge(to_dev(torch, unit_gauge(dims)))
+    with pytest.raises(bms.BmsError) as e:
+        bms.bms_apply_mdagm(c.h, 0.1, 0.0, 2, v, v)  # aliasing
+    assert e.value.code == bms.BMS_EINVAL
+    with pytest.raises(bms.BmsError) as e:
+        bms.bms_apply_hop(c.h, 2, 2, v, torch.empty_like(v))
+    assert e.value.code == bms.BMS_EINVAL

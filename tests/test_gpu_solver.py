@@ -1,0 +1,141 @@
+"""Parity of the HIP block multi-shift solver (Algorithm 1) with the oracle.
+
+P1 (hard): every column of every shift has true FP64 relative residual
+           |b - (A + s) x| / |b| <= tol, recomputed here with the oracle operator.
+P2:        X^(s) within rtol of the oracle's multi-shift CG solution at 1e-13;
+           the GPU runs at tol 1e-12 so that the difference is set by the
+           conditioning bound kappa_s * 1e-12 (kappa_s <= (16+m^2+s)/(m^2+s)).
+P3:        FP64 iteration count within +-2 of the oracle's Algorithm 1.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import rel, to_dev, to_np, torch_gpu
+from oracle import freefield as F
+from oracle import oracle as O
+from paper_1808_01829_amd.inputs import configs, gaussian_block, random_gauge, unit_gauge
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_gpu()
+
+
+def _setup(name, dims=None, n=None):
+    w = configs.WORKLOADS[name]
+    dims = dims or w["dims"]
+    n = n or w["n"]
+    U = random_gauge(dims, w["eps"], 1000 * w["id"])
+    B = gaussian_block(dims, n, 1000 * w["id"] + 1)
+    r = configs.workload_coefficients(name)
+    return dims, n, U, B, w["mass"], r
+
+
+def _ctx(torch, dims, U, bc=BC):
+    from paper_1808_01829_amd import bms
+    c = bms.Context(dims, bc)
+    c.set_gauge(to_dev(torch, U))
+    return c
+
+
+def _kappa(mass, shifts):
+    m2 = mass * mass
+    return (16 + m2 + np.asarray(shifts)) / (m2 + np.asarray(shifts))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_solver_parity_f64(torch, name):
+    dims, n, U, B, m, r = _setup(name)
+    c = _ctx(torch, dims, U)
+    X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-12, max_iter=5000)
+    X = to_np(X)
+    # P1 with the oracle operator
+    tr = O.true_residuals(dims, BC, U, m, r.beta, B, X)
+    assert tr.max() <= 1e-12
+    assert abs(st["max_true_residual"] - tr.max()) <= 1e-3 * tr.max() + 1e-16
+    # P2
+    Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-13)
+    for s in range(len(r.beta)):
+        bound = max(1e-9, 5 * _kappa(m, r.beta[s]) * 1e-12)
+        assert np.linalg.norm(X[s] - Xo[s]) <= bound * np.linalg.norm(Xo[s])
+    # P3
+    oo = O.sbcgrq_lattice(dims, BC, U, m, r.beta, B, 1e-12)
+    assert abs(st["iterations"] - oo["iters"]) <= 2
+
+
+def test_solver_tol_1e10_and_action(torch):
+    dims, n, U, B, m, r = _setup("c2")
+    c = _ctx(torch, dims, U)
+    Bd = to_dev(torch, B)
+    X, st = c.solve(m, r.beta, Bd, tol=1e-10)
+    X = to_np(X)
+    assert st["converged"] and st["max_true_residual"] <= 1e-10
+    tr = O.true_residuals(dims, BC, U, m, r.beta, B, X)
+    assert tr.max() <= 1e-10
+    S = c.action(r.a0, r.alpha, Bd, to_dev(torch, X))
+    So = O.action(B, X, r.a0, r.alpha)
+    assert np.allclose(S, So, rtol=1e-12)
+    # the action is quadratic in the residual: vs the 1e-13 oracle solution
+    Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-13)
+    assert np.allclose(S, O.action(B, Xo, r.a0, r.alpha), rtol=1e-9)
+
+
+@pytest.mark.parametrize("dims,n", [((4, 4, 4, 4), 3), ((4, 6, 2, 8), 5), ((2, 4, 2, 6), 2),
+                                    ((8, 8, 8, 8), 16), ((8, 8, 4, 4), 32)])
+def test_solver_shapes(torch, dims, n):
+    r = configs.workload_coefficients("c2")
+    U = random_gauge(dims, 0.5, 77)
+    B = gaussian_block(dims, n, 78)
+    c = _ctx(torch, dims, U)
+    X, st = c.solve(0.05, r.beta, to_dev(torch, B), tol=1e-10, max_iter=3000)
+    tr = O.true_residuals(dims, BC, U, 0.05, r.beta, B, to_np(X))
+    assert tr.max() <= 1e-10
+
+
+def test_unsorted_duplicate_shifts(torch):
+    dims, n, U, B, m, r = _setup("c2", dims=(4, 4, 4, 4))
+    sh = [r.beta[5], r.beta[0], r.beta[5], 2.0, r.beta[0]]
+    c = _ctx(torch, dims, U)
+    X, st = c.solve(m, sh, to_dev(torch, B), tol=1e-11)
+    X = to_np(X)
+    tr = O.true_residuals(dims, BC, U, m, sh, B, X)
+    assert tr.max() <= 1e-11
+    assert rel(X[0], X[2]) < 1e-9 and rel(X[1], X[4]) < 1e-9
+
+
+def test_free_field_exact(torch):
+    dims, n = (16, 16, 16, 16), 8
+    B = gaussian_block(dims, n, 9)
+    sh = [1e-3, 0.05, 1.0, 7.0]
+    c = _ctx(torch, dims, unit_gauge(dims))
+    X, st = c.solve(0.02, sh, to_dev(torch, B), tol=1e-12)
+    X = to_np(X)
+    for s, sig in enumerate(sh):
+        xf = F.solve(dims, BC, 0.02, sig, B)
+        assert np.linalg.norm(X[s] - xf) <= 1e-9 * np.linalg.norm(xf)
+
+
+def test_errors_and_limits(torch):
+    from paper_1808_01829_amd import bms
+    dims, n, U, B, m, r = _setup("c2", dims=(4, 4, 4, 4))
+    c = _ctx(torch, dims, U)
+    # linearly dependent columns: rank-deficient block
+    Bd = B.copy()
+    Bd[..., 2] = Bd[..., 0]
+    with pytest.raises(bms.BmsError) as e:
+        c.solve(m, r.beta, to_dev(torch, Bd))
+    assert e.value.code == bms.BMS_EBREAKDOWN
+    # too few iterations
+    X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-10, max_iter=5, raise_on_error=False)
+    assert st["status"] == bms.BMS_ENOCONV and st["iterations"] == 5
+    # bad arguments
+    for kw in [dict(shifts=[-1.0]), dict(shifts=[0.1] * 65)]:
+        with pytest.raises(bms.BmsError) as e:
+            c.solve(m, kw["shifts"], to_dev(torch, B))
+        assert e.value.code == bms.BMS_EINVAL
+    # the context still works afterwards
+    X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-10)
+    assert st["converged"]
