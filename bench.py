@@ -56,6 +56,20 @@ def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s):
                            per_vector_iters)))
 
 
+def per_vector(ctx, bms, m, r, Bd, tol, cols, torch):
+    """Same library, n = 1, FP64, one column at a time (multi-shift CG)."""
+    iters = []
+    opts = bms.bms_default_opts()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(cols):
+        _, st = ctx.solve(m, r.beta, Bd[..., j:j + 1].contiguous(), tol=tol, max_iter=50000,
+                          opts=opts)
+        iters.append(st["iterations"])
+    torch.cuda.synchronize()
+    return iters, cols / (time.perf_counter() - t0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +80,8 @@ def main():
     ap.add_argument("--baseline-cols", type=int, default=2,
                     help="columns solved one at a time (n = 1, FP64) for the per-vector rate")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--other-precision", type=int, default=1,
+                    help="also time this many solves in the other precision (reported aside)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,23 +153,40 @@ def main():
                     unit="GB/s", frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None)
 
     # per-vector baseline: same library, n = 1, FP64, one column at a time
-    pv_iters = []
-    t0 = time.perf_counter()
-    pvopts = bms.bms_default_opts()
-    for j in range(args.baseline_cols):
-        _, stv = ctx.solve(m, r.beta, Bd[..., j:j + 1].contiguous(), tol=tol, max_iter=50000,
-                           opts=pvopts)
-        pv_iters.append(stv["iterations"])
-    torch.cuda.synchronize()
-    pv_time = time.perf_counter() - t0
-    pv_rate = args.baseline_cols / pv_time
-    log("bench: per-vector FP64 %d columns in %.3f s, iterations %s" % (
-        args.baseline_cols, pv_time, pv_iters))
+    pv_iters = [0]
+    pv_rate = float("nan")
+    if args.baseline_cols > 0:
+        pv_iters, pv_rate = per_vector(ctx, bms, m, r, Bd, tol, args.baseline_cols, torch)
+        log("bench: per-vector FP64 %d columns, %.4f RHS-solves/s, iterations %s" % (
+            args.baseline_cols, pv_rate, pv_iters))
+
+    other = None
+    if args.other_precision > 0:
+        op = "mixed" if prec == "f64" else "f64"
+        oo = bms.bms_default_opts()
+        oo.precision = bms.BMS_PREC_F64 if op == "f64" else bms.BMS_PREC_MIXED
+        if w.get("reliable"):
+            oo.reliable_interval = w["reliable"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        osolved, ost = 0, None
+        for i in range(args.other_precision):
+            _, ost = ctx.solve(m, r.beta, Bd, tol=tol, max_iter=20000, opts=oo, raise_on_error=False)
+            res = np.asarray(ost["true_residual"])
+            osolved += int(np.sum(np.all(res <= tol, axis=0)))
+        torch.cuda.synchronize()
+        ot = time.perf_counter() - t0
+        other = dict(precision=op, value=round(osolved / ot, 4), unit="RHS-solves/s",
+                     s_per_solve=round(ot / args.other_precision, 3),
+                     iterations=ost["iterations"], refine_iterations=ost["refine_iterations"],
+                     reliable_updates=ost["reliable_updates"],
+                     max_true_residual=ost["max_true_residual"])
+        log("bench: %s: %s" % (op, other))
 
     cpu = None
     if not args.no_cpu:
         try:
-            cpu = cpu_oracle_sample(U, B, w, r, int(np.mean(pv_iters)), args.cpu_seconds)
+            cpu = cpu_oracle_sample(U, B, w, r, int(np.mean(pv_iters or iters)), args.cpu_seconds)
         except Exception as e:  # the oracle is optional for the measurement
             log("bench: cpu baseline failed: %r" % (e,))
 
@@ -170,9 +203,11 @@ def main():
                     lattice=list(dims), n_pf=n, n_shifts=r.n_poles, tol=tol, precision=prec),
         roofline=roofline,
         cpu_baseline=cpu,
-        per_vector=dict(value=round(pv_rate, 4), unit="RHS-solves/s", columns=args.baseline_cols,
+        per_vector=dict(value=round(pv_rate, 4) if pv_rate == pv_rate else None,
+                        unit="RHS-solves/s", columns=args.baseline_cols,
                         iterations=pv_iters, dtype="f64"),
-        block_over_per_vector=round(value / pv_rate, 3),
+        block_over_per_vector=round(value / pv_rate, 3) if pv_rate == pv_rate else None,
+        other_precision=other,
         iterations=iters, max_true_residual=maxres,
         dslash_gbs=kernels.get("hop", {}).get("gbs"),
         kernels=kernels,

@@ -144,10 +144,11 @@ int bms_apply_mdagm(bms_ctx* ctx, double mass, double sigma, int n, const void* 
  * for s = 0..n_shifts-1 and all n columns of B at once.
  *   shifts: host array, each >= 0, any order; the smallest one drives the
  *           unshifted recurrence (sigma_0). Duplicates are allowed.
- *   tol:    target relative residual per column and shift, > 0. The loop runs
- *           until every shifted residual estimate |delta^(s) e_i| / |b_i| is
- *           below tol; then the true FP64 residuals are computed and, in MIXED
- *           precision, shifts above tol are refined by defect correction.
+ *   tol:    target relative residual per column and shift, in (0, 1). The
+ *           loop runs until every shifted residual estimate |delta^(s) e_i| / |b_i|
+ *           is below tol/2 (a margin for the drift between the recurrence and
+ *           the true residual); then the true FP64 residuals are computed and
+ *           shifts above tol are refined by defect correction.
  *   B:      device block [cb][color][rhs] complex128 (even sites), full column rank.
  *   X:      device output [shift][cb][color][rhs] complex128.
  *   opts:   NULL for defaults. stats: NULL or caller struct.
@@ -208,6 +209,16 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
 #define BMS_NKERNELS 5
 
 int bms_timing_enable(bms_ctx* ctx, int enable);
+
+/*
+ * Kernel variant selection (what bms_autotune chooses). For BMS_KERNEL_UPDATE
+ * at n = 8 or 16: 0 = four row chunks per work-group with both coefficient
+ * columns in registers, 1 = two chunks, one column at a time, 2 = four
+ * chunks, one column at a time (the built-in default), 3 = two chunks, both
+ * columns; -1 restores the built-in default. Other widths and kernels ignore the setting. Results do
+ * not depend on the variant beyond rounding order.
+ */
+int bms_set_variant(bms_ctx* ctx, int kernel, int variant);
 int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,
                     double* bytes);
 

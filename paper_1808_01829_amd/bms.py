@@ -41,7 +41,7 @@ KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small"]
 
 EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create", "bms_destroy",
            "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",
-           "bms_force", "bms_timing_enable", "bms_timing_read"]
+           "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant"]
 
 
 class bms_opts(ctypes.Structure):
@@ -91,6 +91,7 @@ def _lib():
         L.bms_action.argtypes = [vp, i, i, d, dp, vp, vp, dp]
         L.bms_force.argtypes = [vp, i, i, dp, vp, vp, i]
         L.bms_timing_enable.argtypes = [vp, i]
+        L.bms_set_variant.argtypes = [vp, i, i]
         L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         for f in EXPORTS:
             if f not in ("bms_default_opts", "bms_error_string", "bms_last_error"):
@@ -206,6 +207,10 @@ def bms_timing_enable(ctx, enable=True):
     _check(ctx, _lib().bms_timing_enable(ctx, 1 if enable else 0))
 
 
+def bms_set_variant(ctx, kernel, variant):
+    _check(ctx, _lib().bms_set_variant(ctx, int(kernel), int(variant)))
+
+
 def bms_timing_read(ctx, kernel):
     """Returns (milliseconds, launches, algorithmic bytes) accumulated for a kernel class."""
     ms, nl, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
@@ -280,6 +285,9 @@ class Context:
     def action(self, a0, alpha, B, X):
         n = B.shape[2]
         return bms_action(self.h, n, a0, list(alpha), B, X)
+
+    def set_variant(self, kernel, variant):
+        bms_set_variant(self.h, kernel, variant)
 
     def timing(self, enable=True):
         bms_timing_enable(self.h, enable)

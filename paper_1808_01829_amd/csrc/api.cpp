@@ -1,6 +1,7 @@
 // C-ABI entry points: context lifecycle, validation, gauge import, operator.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -227,5 +228,13 @@ extern "C" int bms_timing_read(const bms_ctx* c, int kernel, double* ms, long lo
   if (ms) *ms = c->kt_ms[kernel];
   if (launches) *launches = c->kt_launches[kernel];
   if (bytes) *bytes = c->kt_bytes[kernel];
+  return BMS_OK;
+}
+
+extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
+  if (!c) return BMS_EINVAL;
+  if (kernel != BMS_KERNEL_UPDATE) return set_err(c, BMS_EINVAL, "no variants for kernel %d", kernel);
+  if (variant < -1 || variant > 3) return set_err(c, BMS_EINVAL, "variant must be in [-1, 3]");
+  c->update_variant = variant;
   return BMS_OK;
 }

@@ -4,7 +4,10 @@
 
 #include "internal.h"
 
-#define UPDATE_NCH 4  // row chunks per work-group in the fused update
+#define UPDATE_NCH 4   // row chunks per work-group in the fused update
+#define RED_GROUP 32   // blocks per first-level group of the grid reductions
+#define CNT_STRIDE 64  // ints per reduction counter set (1 + up to 32 groups, padded)
+#define MAX_RED_BLOCKS 1024
 
 template <typename T, typename TX>
 struct UpdateArgs {
@@ -21,17 +24,34 @@ struct UpdateArgs {
   int xidx[BMS_MAX_SHIFTS];
 };
 
+// run_if: the kernel does nothing unless *run_if is non-zero (NULL: always runs)
 template <typename T>
 hipError_t launch_cholqr_gram(hipStream_t st, int rows, int n, const void* Q, const void* W,
                               const double2* alpha, double2* G, double2* partials, int* counter,
-                              int nb, const int* skip);
+                              int nb, const int* run_if);
 template <typename T, typename TX>
 hipError_t launch_update(hipStream_t st, const UpdateArgs<T, TX>& a);
+// variant 0: both coefficient columns in registers; 1: one at a time
+template <typename T, typename TX>
+hipError_t launch_update_fast(hipStream_t st, const UpdateArgs<T, TX>& a, int variant);
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
                               double2* out, double2* partials, int* counter, int nb);
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,
                          const void* B, const void* X, double2* out, double2* partials,
                          int* counter, int nb);
+
+hipError_t launch_resid_block(hipStream_t st, int rows, int n, const void* B, const void* Y,
+                              const double* cs, const double* cb, void* R, const int* skip);
+hipError_t launch_axpy_cols(hipStream_t st, int rows, int n, void* X, const void* E,
+                            const double* cs);
+hipError_t launch_gather_col(hipStream_t st, int rows, int n, int col, const void* src, void* dst);
+hipError_t launch_scatter_axpy_col(hipStream_t st, int rows, int n, int col, void* X,
+                                   const void* e, double scale);
+hipError_t launch_flush(hipStream_t st, int rows, int n, int ns, void* X32, void* X64,
+                        const int* xmap, const int* skip);
+template <typename TO>
+hipError_t launch_block_matmul_d(hipStream_t st, int rows, int n, const void* X, const double2* M,
+                                 void* Y, const int* skip);
 
 // ---- small n x n FP64 state of the solver (device) ----------------------
 // All matrices are row-major n x n double2. Double-buffered entries are
@@ -45,7 +65,7 @@ struct SmallState {
   double2* beta_s;  // [ns][n*n] beta^(s)
   double2* alpha_s; // [ns][n*n] alpha^(s)
   double* norm0;    // [n]       |b_i|
-  double2* Ggram;   // [n*n]     output of the P^H W Gram
+  double2* G4;      // [4][n*n]  P^H W, Q^H W, W^H W, Q^H Q of the iteration
   double2* Gqr;     // [n*n]     output of the V^H V Gram
   double2* tmp;     // [n*n]     scratch
   int* counter;     // grid-completion counter of the rho kernel
@@ -64,9 +84,17 @@ hipError_t launch_small_init(hipStream_t st, const SmallParams& p, SmallState s,
                              const double2* Gb_in, double2* Rinv_out);
 hipError_t launch_small_init_pass2(hipStream_t st, const SmallParams& p, SmallState s,
                                    SolverFlags* fl, const double2* Gb_in, double2* Rinv_out);
+// reliable update: from G = R0^H R0 of the true residual, delta_k = chol(G)^H
+// and Rinv_out = delta_k^-1 (so that Q_k = R0 Rinv_out)
+hipError_t launch_small_reliable(hipStream_t st, const SmallParams& p, SmallState s,
+                                 SolverFlags* fl, const double2* Gin, double2* Rinv_out);
 template <typename T>
-hipError_t launch_small_alpha(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                              cplx<T>* Mx);
+hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
+                             cplx<T>* Mx, cplx<T>* Mp);
 template <typename T>
-hipError_t launch_small_rho(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                            cplx<T>* Mp);
+hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
+                                     SolverFlags* fl, cplx<T>* Mp);
+template <typename T>
+hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const void* Q,
+                        const void* W, double2* G4, double2* partials, int* counter, int nb,
+                        const int* skip);

@@ -23,23 +23,50 @@ __device__ __forceinline__ RowRange block_rows(int rows, int per_block) {
   return r;
 }
 
-// Deterministic completion of a grid-wide sum: every block has written its
-// P-element partial; the block that finishes last adds them in block order.
+// Deterministic completion of a grid-wide sum in two levels: every block has
+// written its P-element partial; the last block of each group of RED_GROUP
+// blocks adds its group's partials in block order into a group partial, and
+// the last group adds the group partials in group order. The summation order
+// does not depend on which block finishes last. counter[0] is the top-level
+// counter, counter[1 + g] the one of group g; all are left at zero.
+// partials must hold (gridDim.x + ceil(gridDim.x / RED_GROUP)) * P entries.
 __device__ void last_block_sum(double2* __restrict__ partials, double2* __restrict__ out, int P,
                                int* __restrict__ counter) {
   __shared__ int is_last;
+  const int nb = gridDim.x;
+  const int ng = (nb + RED_GROUP - 1) / RED_GROUP;
+  const int g = blockIdx.x / RED_GROUP;
+  const int gsize = min(RED_GROUP, nb - g * RED_GROUP);
+  double2* gpart = partials + (size_t)nb * P;
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+  if (threadIdx.x == 0) is_last = atomicAdd(&counter[1 + g], 1) == gsize - 1;
   __syncthreads();
   if (!is_last) return;
   __threadfence();
   for (int p = threadIdx.x; p < P; p += BMS_WG) {
     double2 s = make_double2(0, 0);
-    for (int b = 0; b < (int)gridDim.x; ++b) s = cadd(s, partials[(size_t)b * P + p]);
+    for (int b = g * RED_GROUP; b < g * RED_GROUP + gsize; ++b)
+      s = cadd(s, partials[(size_t)b * P + p]);
+    if (ng == 1)
+      out[p] = s;
+    else
+      gpart[(size_t)g * P + p] = s;
+  }
+  if (threadIdx.x == 0) atomicExch(&counter[1 + g], 0);
+  if (ng == 1) return;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(&counter[0], 1) == ng - 1;
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  for (int p = threadIdx.x; p < P; p += BMS_WG) {
+    double2 s = make_double2(0, 0);
+    for (int q = 0; q < ng; ++q) s = cadd(s, gpart[(size_t)q * P + p]);
     out[p] = s;
   }
-  if (threadIdx.x == 0) atomicExch(counter, 0);
+  if (threadIdx.x == 0) atomicExch(&counter[0], 0);
 }
 
 // Accumulate sum_r conj(xs[r][i]) ys[r][j] over the nr rows staged in LDS.
@@ -141,8 +168,8 @@ __global__ __launch_bounds__(BMS_WG) void k_cholqr_gram(int rows, int n, int per
                                                         double2* __restrict__ G,
                                                         double2* __restrict__ partials,
                                                         int* __restrict__ counter,
-                                                        const int* __restrict__ skip) {
-  if (skip && *skip) return;
+                                                        const int* __restrict__ run_if) {
+  if (run_if && !*run_if) return;
   __shared__ double2 ws[BMS_WG], vs[BMS_WG];
   __shared__ double2 red[4 * BMS_WG];
   RowRange rr = block_rows(rows, per_block);
@@ -413,3 +440,612 @@ INST(float)
 INST(double)
 template hipError_t launch_update<double, double>(hipStream_t, const UpdateArgs<double, double>&);
 template hipError_t launch_update<float, float>(hipStream_t, const UpdateArgs<float, float>&);
+
+// ---- one-pass Grams of an iteration -----------------------------------------
+// G4 = [P^H W, Q^H W, W^H W, Q^H Q] (FP64, 4 n x n blocks) in one pass over
+// the rows, so that V^H V for V = Q - W alpha follows from the expansion
+//   V^H V = Q^H Q - (Q^H W) alpha - alpha^H (Q^H W)^H + alpha^H (W^H W) alpha
+// without a second pass. Register blocking: a thread owns a TB x TB tile of
+// one Gram; W^H W and Q^H Q are Hermitian and only their upper tiles are
+// computed (the reduction mirrors them).
+namespace {
+
+struct TileId {
+  int g, ti, tj;
+};
+
+__device__ __forceinline__ TileId decode_tile(int r, int nt) {
+  const int full = nt * nt, half = nt * (nt + 1) / 2;
+  TileId d;
+  if (r < full) d.g = 0;
+  else if ((r -= full) < full) d.g = 1;
+  else if ((r -= full) < half) d.g = 2;
+  else {
+    r -= half;
+    d.g = 3;
+  }
+  if (d.g < 2) {
+    d.ti = r / nt;
+    d.tj = r - d.ti * nt;
+  } else {  // r-th upper tile in row-major order
+    d.ti = 0;
+    while (r >= nt - d.ti) {
+      r -= nt - d.ti;
+      ++d.ti;
+    }
+    d.tj = d.ti + r;
+  }
+  return d;
+}
+
+template <typename T, int TB>
+__global__ __launch_bounds__(BMS_WG) void k_gram4(int rows, int n, int per_block,
+                                                  const cplx<T>* __restrict__ P,
+                                                  const cplx<T>* __restrict__ Q,
+                                                  const cplx<T>* __restrict__ W,
+                                                  double2* __restrict__ G4,
+                                                  double2* __restrict__ partials,
+                                                  int* __restrict__ counter,
+                                                  const int* __restrict__ skip) {
+  using C_ = cplx<T>;
+  if (skip && *skip) return;
+  // LDS: the staged rows during the sweep, then the row-group reduction
+  constexpr int RED = TB == 4 ? 2048 : 1024;  // double2 entries
+  // staged rows padded to n+1 entries and the three arrays staggered, so that
+  // the rows and arrays a wave reads fall in different LDS banks
+  constexpr int STAGE_BYTES = 3 * (2 * BMS_WG + 2) * (int)sizeof(C_);
+  constexpr int SM_BYTES = RED * 16 > STAGE_BYTES ? RED * 16 : STAGE_BYTES;
+  __shared__ __align__(16) unsigned char smem[SM_BYTES];
+  const int C = BMS_WG / n;
+  const int RS = n > 1 ? n + 1 : 1;
+  const int AS = C * RS + 1;
+  C_* ps = (C_*)smem;
+  C_* qs = ps + AS;
+  C_* wsm = qs + AS;
+  const int nt = n / TB;
+  const int tiles = 2 * nt * nt + nt * (nt + 1);
+  const int nrg = BMS_WG / tiles;
+  const int t = threadIdx.x;
+  const int rg = t / tiles, tl = t - (t / tiles) * tiles;
+  const TileId id = decode_tile(tl, nt);
+  const C_* xs = (id.g == 0) ? ps : ((id.g == 2) ? wsm : qs);
+  const C_* ys = (id.g == 3) ? qs : wsm;
+  RowRange rr = block_rows(rows, per_block);
+  const int lw = (t / n) * RS + (t - (t / n) * n);  // this thread's staging slot
+  double2 acc[TB][TB];
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = make_double2(0, 0);
+  // register prefetch of the next chunk while the current one is reduced
+  C_ np_ = czero<C_>(), nq_ = czero<C_>(), nw_ = czero<C_>();
+  if (rr.r0 < rr.r1 && t < min(C, rr.r1 - rr.r0) * n) {
+    size_t o = (size_t)rr.r0 * n + t;
+    np_ = P[o];
+    nq_ = Q[o];
+    nw_ = W[o];
+  }
+  for (int r0 = rr.r0; r0 < rr.r1; r0 += C) {
+    int nr = min(C, rr.r1 - r0);
+    if (t < nr * n) {
+      ps[lw] = np_;
+      qs[lw] = nq_;
+      wsm[lw] = nw_;
+    }
+    __syncthreads();
+    int r1 = r0 + C;
+    if (r1 < rr.r1 && t < min(C, rr.r1 - r1) * n) {
+      size_t o = (size_t)r1 * n + t;
+      np_ = P[o];
+      nq_ = Q[o];
+      nw_ = W[o];
+    }
+    if (rg < nrg) {
+      for (int r = rg; r < nr; r += nrg) {
+        double2 xv[TB], yv[TB];
+#pragma unroll
+        for (int a = 0; a < TB; ++a) {
+          xv[a] = to_d(xs[r * RS + id.ti * TB + a]);
+          yv[a] = to_d(ys[r * RS + id.tj * TB + a]);
+        }
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) acc[a][b] = cjfma(xv[a], yv[b], acc[a][b]);
+      }
+    }
+    __syncthreads();
+  }
+  const int nn = n * n;
+  double2* part = partials + (size_t)blockIdx.x * 4 * nn;
+  double2* red = (double2*)smem;
+  if (TB == 4 && nrg == 1) {
+    // one row group: write the tile straight from registers
+    if (rg < nrg) {
+#pragma unroll
+      for (int a = 0; a < TB; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+          int i = id.ti * TB + a, j = id.tj * TB + b;
+          part[id.g * nn + i * n + j] = acc[a][b];
+          if (id.g >= 2 && id.ti != id.tj) part[id.g * nn + j * n + i] = cconj(acc[a][b]);
+        }
+    }
+  } else {
+    if (TB == 4) {
+      // few row groups: accumulate them one after another in tiles*16 entries
+      for (int g = 0; g < nrg; ++g) {
+        if (rg == g) {
+#pragma unroll
+          for (int a = 0; a < TB; ++a)
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+              int e = tl * TB * TB + a * TB + b;
+              red[e] = g == 0 ? acc[a][b] : cadd(red[e], acc[a][b]);
+            }
+        }
+        __syncthreads();
+      }
+    } else {
+      if (rg < nrg) {
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) red[(rg * tiles + tl) * TB * TB + a * TB + b] = acc[a][b];
+      }
+      __syncthreads();
+    }
+    for (int e = t; e < tiles * TB * TB; e += BMS_WG) {
+      int tile = e / (TB * TB), ab = e - tile * TB * TB;
+      double2 sum;
+      if (TB == 4) {
+        sum = red[e];
+      } else {
+        sum = make_double2(0, 0);
+        for (int q = 0; q < nrg; ++q) sum = cadd(sum, red[(q * tiles + tile) * TB * TB + ab]);
+      }
+      TileId d = decode_tile(tile, nt);
+      int a = ab / TB, b = ab - (ab / TB) * TB;
+      int i = d.ti * TB + a, j = d.tj * TB + b;
+      part[d.g * nn + i * n + j] = sum;
+      if (d.g >= 2 && d.ti != d.tj) part[d.g * nn + j * n + i] = cconj(sum);
+    }
+  }
+  last_block_sum(partials, G4, 4 * nn, counter);
+}
+
+}  // namespace
+
+int gram4_tb(int n) { return (n >= 16 && n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1); }
+
+bool gram4_fits(int n) {
+  int tb = gram4_tb(n), nt = n / tb;
+  return 2 * nt * nt + nt * (nt + 1) <= BMS_WG;
+}
+
+template <typename T>
+hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const void* Q,
+                        const void* W, double2* G4, double2* partials, int* counter, int nb,
+                        const int* skip) {
+  int per = rows_per_block(rows, nb);
+  const cplx<T>* p = (const cplx<T>*)P;
+  const cplx<T>* q = (const cplx<T>*)Q;
+  const cplx<T>* w = (const cplx<T>*)W;
+  if (!gram4_fits(n)) {  // four pairwise passes
+    const cplx<T>* xs[4] = {p, q, w, q};
+    const cplx<T>* ys[4] = {w, w, w, q};
+    for (int g = 0; g < 4; ++g) {
+      k_gram<T><<<nb, BMS_WG, 0, st>>>(rows, n, per, xs[g], ys[g], G4 + (size_t)g * n * n,
+                                       partials, counter, skip);
+    }
+    return hipGetLastError();
+  }
+  switch (gram4_tb(n)) {
+    case 4:
+      k_gram4<T, 4><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, G4, partials, counter, skip);
+      break;
+    case 2:
+      k_gram4<T, 2><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, G4, partials, counter, skip);
+      break;
+    default:
+      k_gram4<T, 1><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, G4, partials, counter, skip);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_gram4<double>(hipStream_t, int, int, const void*, const void*,
+                                         const void*, double2*, double2*, int*, int, const int*);
+template hipError_t launch_gram4<float>(hipStream_t, int, int, const void*, const void*,
+                                        const void*, double2*, double2*, int*, int, const int*);
+
+// ---- fused update, specialised on the block width ---------------------------
+// Same arithmetic as k_update. Thread (row lr, column j) of each of NCH chunks
+// of C = 256/N rows; the j-th columns of alpha_k, rho_k^-1 (FP64) and of each
+// shift's Mx, Mp are held in registers, so the only LDS traffic is the row
+// broadcast of the block being multiplied. All NCH chunks are staged per sync.
+namespace {
+
+__device__ __forceinline__ int next_active(const SolverFlags* fl, int s, int ns) {
+  for (++s; s < ns; ++s)
+    if (fl->active[s]) break;
+  return s;
+}
+
+// SPLIT = 0: the j-th columns of Mx and Mp both live in registers;
+// SPLIT = 1: one at a time (half the registers, twice the LDS reads).
+// The next active shift's P^(s) and X^(s) are prefetched into registers
+// while the current one is combined.
+template <typename T, typename TX, int N, int NCH, int SPLIT>
+__global__ __launch_bounds__(BMS_WG) void k_update_n(UpdateArgs<T, TX> a) {
+  using C_ = cplx<T>;
+  using CX = cplx<TX>;
+  const SolverFlags* fl = a.flags;
+  if (fl->halted) return;
+  constexpr int C = BMS_WG / N;
+  const int t = threadIdx.x;
+  const int lr = t / N, j = t % N;
+  const bool live = t < C * N;
+  const int rbase = blockIdx.x * C * NCH;
+  const int rows = a.rows;
+  const int ns = a.ns;
+  bool act[NCH];
+  size_t off[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    int r = rbase + ch * C + lr;
+    act[ch] = live && r < rows;
+    off[ch] = (size_t)(rbase + ch * C) * N + t;
+  }
+  C_ qn[NCH];
+  if constexpr (N == 1) {
+    // no row mixing: every product is a scalar multiplication
+    double2 al = a.alpha[0], ri = a.rhoinv[0];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (!act[ch]) continue;
+      double2 v = csub(to_d(a.Q[off[ch]]), cmul(to_d(a.W[off[ch]]), al));
+      qn[ch] = from_d<C_>(cmul(v, ri));
+      a.Q[off[ch]] = qn[ch];
+    }
+    for (int s = 0; s < ns; ++s) {
+      if (!fl->active[s]) continue;
+      C_* P = a.P + (size_t)s * rows;
+      CX* X = a.X + (size_t)a.xidx[s] * rows;
+      C_ mx = a.Mx[s], mp = a.Mp[s];
+      C_ p[NCH];
+      CX x[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        if (!act[ch]) continue;
+        p[ch] = P[off[ch]];
+        x[ch] = X[off[ch]];
+      }
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        if (!act[ch]) continue;
+        C_ dx = cmul(p[ch], mx);
+        X[off[ch]] = cmk<CX>(x[ch].x + (TX)dx.x, x[ch].y + (TX)dx.y);
+        P[off[ch]] = cfma(p[ch], mp, qn[ch]);
+      }
+    }
+    return;
+  } else {
+    // rows padded to N + 1 entries: the rows a wave reads sit in different banks
+    constexpr int RS = N + 1;
+    constexpr int CS = C * RS;
+    __shared__ double2 buf[NCH * CS];
+    __shared__ C_ ps[NCH * CS];
+    const int lw = lr * RS + j;  // this thread's LDS slot inside a chunk
+    double2 mcol[N];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      if (act[ch]) buf[ch * CS + lw] = to_d(a.W[off[ch]]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) mcol[k] = a.alpha[k * N + j];
+    __syncthreads();
+    double2 v[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (!act[ch]) continue;
+      double2 wa = make_double2(0, 0);
+      const double2* wr = buf + ch * CS + lr * RS;
+#pragma unroll
+      for (int k = 0; k < N; ++k) wa = cfma(wr[k], mcol[k], wa);
+      v[ch] = csub(to_d(a.Q[off[ch]]), wa);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      if (act[ch]) buf[ch * CS + lw] = v[ch];
+#pragma unroll
+    for (int k = 0; k < N; ++k) mcol[k] = a.rhoinv[k * N + j];
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (!act[ch]) continue;
+      double2 q = make_double2(0, 0);
+      const double2* vr = buf + ch * CS + lr * RS;
+#pragma unroll
+      for (int k = 0; k < N; ++k) q = cfma(vr[k], mcol[k], q);
+      qn[ch] = from_d<C_>(q);
+      a.Q[off[ch]] = qn[ch];
+    }
+    // shifts, with the next active shift's rows prefetched
+    C_ pn[NCH];
+    CX xn[NCH], xv[NCH];
+    int s = next_active(fl, -1, ns);
+    if (s < ns) {
+      const C_* P = a.P + (size_t)s * rows * N;
+      const CX* X = a.X + (size_t)a.xidx[s] * rows * N;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (act[ch]) {
+          pn[ch] = P[off[ch]];
+          xn[ch] = X[off[ch]];
+        }
+    }
+    while (s < ns) {
+      const int s2 = next_active(fl, s, ns);
+      C_* P = a.P + (size_t)s * rows * N;
+      CX* X = a.X + (size_t)a.xidx[s] * rows * N;
+      const C_* Mx = a.Mx + (size_t)s * N * N;
+      const C_* Mp = a.Mp + (size_t)s * N * N;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (act[ch]) {
+          ps[ch * CS + lw] = pn[ch];
+          xv[ch] = xn[ch];
+        }
+      __syncthreads();
+      if (s2 < ns) {
+        const C_* P2 = a.P + (size_t)s2 * rows * N;
+        const CX* X2 = a.X + (size_t)a.xidx[s2] * rows * N;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+          if (act[ch]) {
+            pn[ch] = P2[off[ch]];
+            xn[ch] = X2[off[ch]];
+          }
+      }
+      if constexpr (SPLIT) {
+        C_ m[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) m[k] = Mx[k * N + j];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (!act[ch]) continue;
+          const C_* pr = ps + ch * CS + lr * RS;
+          C_ dx = czero<C_>();
+#pragma unroll
+          for (int k = 0; k < N; ++k) dx = cfma(pr[k], m[k], dx);
+          X[off[ch]] = cmk<CX>(xv[ch].x + (TX)dx.x, xv[ch].y + (TX)dx.y);
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) m[k] = Mp[k * N + j];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (!act[ch]) continue;
+          const C_* pr = ps + ch * CS + lr * RS;
+          C_ np = qn[ch];
+#pragma unroll
+          for (int k = 0; k < N; ++k) np = cfma(pr[k], m[k], np);
+          P[off[ch]] = np;
+        }
+      } else {
+        C_ mx[N], mp[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          mx[k] = Mx[k * N + j];
+          mp[k] = Mp[k * N + j];
+        }
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (!act[ch]) continue;
+          const C_* pr = ps + ch * CS + lr * RS;
+          C_ dx = czero<C_>();
+          C_ np = qn[ch];
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            C_ pk = pr[k];
+            dx = cfma(pk, mx[k], dx);
+            np = cfma(pk, mp[k], np);
+          }
+          X[off[ch]] = cmk<CX>(xv[ch].x + (TX)dx.x, xv[ch].y + (TX)dx.y);
+          P[off[ch]] = np;
+        }
+      }
+      __syncthreads();
+      s = s2;
+    }
+  }
+}
+
+template <typename T, typename TX, int N, int NCH, int SPLIT>
+hipError_t launch_update_n(hipStream_t st, const UpdateArgs<T, TX>& a) {
+  int per = (BMS_WG / N) * NCH;
+  k_update_n<T, TX, N, NCH, SPLIT><<<(a.rows + per - 1) / per, BMS_WG, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T, typename TX>
+hipError_t launch_update_fast(hipStream_t st, const UpdateArgs<T, TX>& a, int variant) {
+  // variant: 0 = NCH 4 both columns, 1 = NCH 2 split, 2 = NCH 4 split, 3 = NCH 2 both
+  switch (a.n) {
+    case 1: return launch_update_n<T, TX, 1, 4, 0>(st, a);
+    case 2: return launch_update_n<T, TX, 2, 4, 0>(st, a);
+    case 4: return launch_update_n<T, TX, 4, 4, 0>(st, a);
+    case 8:
+      switch (variant) {
+        case 1: return launch_update_n<T, TX, 8, 2, 1>(st, a);
+        case 2: return launch_update_n<T, TX, 8, 4, 1>(st, a);
+        case 3: return launch_update_n<T, TX, 8, 2, 0>(st, a);
+        default: return launch_update_n<T, TX, 8, 4, 0>(st, a);
+      }
+    case 16:
+      switch (variant) {
+        case 1: return launch_update_n<T, TX, 16, 2, 1>(st, a);
+        case 2: return launch_update_n<T, TX, 16, 4, 1>(st, a);
+        case 3: return launch_update_n<T, TX, 16, 2, 0>(st, a);
+        default: return launch_update_n<T, TX, 16, 4, 0>(st, a);
+      }
+    default: return launch_update<T, TX>(st, a);
+  }
+}
+
+template hipError_t launch_update_fast<double, double>(hipStream_t,
+                                                       const UpdateArgs<double, double>&, int);
+template hipError_t launch_update_fast<float, float>(hipStream_t, const UpdateArgs<float, float>&,
+                                                     int);
+
+// ---- precision control: reliable updates and defect correction --------------
+namespace {
+
+// R[r][i] = (B[r][i] - Y[r][i]) * cs[i]; a column with cs[i] == 0 is replaced
+// by B[r][i] * cb[i] (a harmless non-zero column for the block solver)
+__global__ __launch_bounds__(BMS_WG) void k_resid_block(int rows, int n, const double2* __restrict__ B,
+                                                        const double2* __restrict__ Y,
+                                                        const double* __restrict__ cs,
+                                                        const double* __restrict__ cb,
+                                                        double2* __restrict__ R,
+                                                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  size_t i = (size_t)blockIdx.x * BMS_WG + threadIdx.x;
+  if (i >= (size_t)rows * n) return;
+  int col = (int)(i % n);
+  double c = cs ? cs[col] : 1.0;
+  R[i] = (c != 0.0 || !cb) ? cscale(csub(B[i], Y[i]), c) : cscale(B[i], cb[col]);
+}
+
+// X[r][i] += E[r][i] * cs[i]
+__global__ __launch_bounds__(BMS_WG) void k_axpy_cols(int rows, int n, double2* __restrict__ X,
+                                                      const double2* __restrict__ E,
+                                                      const double* __restrict__ cs) {
+  size_t i = (size_t)blockIdx.x * BMS_WG + threadIdx.x;
+  if (i >= (size_t)rows * n) return;
+  X[i] = cadd(X[i], cscale(E[i], cs[i % n]));
+}
+
+// X64[xmap[s]] += X32[s]; X32[s] = 0 for every shift (FP32 increments into
+// the FP64 solutions)
+struct FlushArgs {
+  int rows, n, ns;
+  float2* X32;
+  double2* X64;
+  int xmap[BMS_MAX_SHIFTS];
+};
+
+__global__ __launch_bounds__(BMS_WG) void k_flush(FlushArgs a, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  size_t blk = (size_t)a.rows * a.n;
+  size_t i = (size_t)blockIdx.x * BMS_WG + threadIdx.x;
+  if (i >= blk) return;
+  for (int s = 0; s < a.ns; ++s) {
+    float2 v = a.X32[s * blk + i];
+    if (v.x != 0.f || v.y != 0.f) {
+      double2* x = a.X64 + (size_t)a.xmap[s] * blk + i;
+      *x = make_double2(x->x + v.x, x->y + v.y);
+      a.X32[s * blk + i] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// Y = X M with FP64 input X, FP64 M, output in precision TO
+template <typename TO>
+__global__ __launch_bounds__(BMS_WG) void k_block_matmul_d(int rows, int n,
+                                                           const double2* __restrict__ X,
+                                                           const double2* __restrict__ M,
+                                                           cplx<TO>* __restrict__ Y,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double2 xs[BMS_WG];
+  int C = BMS_WG / n;
+  int r0 = blockIdx.x * C;
+  int nr = min(C, rows - r0);
+  int t = threadIdx.x;
+  if (t < nr * n) xs[t] = X[(size_t)r0 * n + t];
+  __syncthreads();
+  if (t < nr * n) {
+    int lr = t / n, j = t - lr * n;
+    double2 acc = make_double2(0, 0);
+    for (int k = 0; k < n; ++k) acc = cfma(xs[lr * n + k], M[k * n + j], acc);
+    Y[(size_t)r0 * n + t] = from_d<cplx<TO>>(acc);
+  }
+}
+
+}  // namespace
+
+static unsigned grid_for(size_t n) { return (unsigned)((n + BMS_WG - 1) / BMS_WG); }
+
+hipError_t launch_resid_block(hipStream_t st, int rows, int n, const void* B, const void* Y,
+                              const double* cs, const double* cb, void* R, const int* skip) {
+  k_resid_block<<<grid_for((size_t)rows * n), BMS_WG, 0, st>>>(
+      rows, n, (const double2*)B, (const double2*)Y, cs, cb, (double2*)R, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols(hipStream_t st, int rows, int n, void* X, const void* E,
+                            const double* cs) {
+  k_axpy_cols<<<grid_for((size_t)rows * n), BMS_WG, 0, st>>>(rows, n, (double2*)X,
+                                                            (const double2*)E, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(hipStream_t st, int rows, int n, int ns, void* X32, void* X64,
+                        const int* xmap, const int* skip) {
+  FlushArgs a;
+  a.rows = rows;
+  a.n = n;
+  a.ns = ns;
+  a.X32 = (float2*)X32;
+  a.X64 = (double2*)X64;
+  for (int s = 0; s < BMS_MAX_SHIFTS; ++s) a.xmap[s] = s < ns ? xmap[s] : 0;
+  k_flush<<<grid_for((size_t)rows * n), BMS_WG, 0, st>>>(a, skip);
+  return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_block_matmul_d(hipStream_t st, int rows, int n, const void* X, const double2* M,
+                                 void* Y, const int* skip) {
+  int C = BMS_WG / n;
+  k_block_matmul_d<TO><<<(rows + C - 1) / C, BMS_WG, 0, st>>>(rows, n, (const double2*)X, M,
+                                                              (cplx<TO>*)Y, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_block_matmul_d<float>(hipStream_t, int, int, const void*,
+                                                 const double2*, void*, const int*);
+template hipError_t launch_block_matmul_d<double>(hipStream_t, int, int, const void*,
+                                                  const double2*, void*, const int*);
+
+// ---- per-column defect correction -----------------------------------------
+namespace {
+__global__ __launch_bounds__(BMS_WG) void k_gather_col(int rows, int n, int col,
+                                                       const double2* __restrict__ src,
+                                                       double2* __restrict__ dst) {
+  int r = blockIdx.x * BMS_WG + threadIdx.x;
+  if (r < rows) dst[r] = src[(size_t)r * n + col];
+}
+__global__ __launch_bounds__(BMS_WG) void k_scatter_axpy_col(int rows, int n, int col,
+                                                             double2* __restrict__ X,
+                                                             const double2* __restrict__ e,
+                                                             double scale) {
+  int r = blockIdx.x * BMS_WG + threadIdx.x;
+  if (r < rows) {
+    size_t o = (size_t)r * n + col;
+    X[o] = cadd(X[o], cscale(e[r], scale));
+  }
+}
+}  // namespace
+
+hipError_t launch_gather_col(hipStream_t st, int rows, int n, int col, const void* src, void* dst) {
+  k_gather_col<<<grid_for(rows), BMS_WG, 0, st>>>(rows, n, col, (const double2*)src,
+                                                 (double2*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_axpy_col(hipStream_t st, int rows, int n, int col, void* X,
+                                   const void* e, double scale) {
+  k_scatter_axpy_col<<<grid_for(rows), BMS_WG, 0, st>>>(rows, n, col, (double2*)X,
+                                                       (const double2*)e, scale);
+  return hipGetLastError();
+}

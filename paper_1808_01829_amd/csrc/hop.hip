@@ -53,53 +53,60 @@ __global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restri
   }
 }
 
-// out(s) = b * sum_k L_k(s) in(nbr_k(s)) + a * aux(s), per column j.
-// One thread per (site, column): lanes of one site share its links (the
-// block operator reads each link once per n columns) and read the n columns
-// of a neighbour as one contiguous run.
-template <typename T>
+// out(s) = b * sum_k L_k(s) in(nbr_k(s)) + a * aux(s) on n columns.
+// One thread per (site, group of R consecutive columns): the lanes of a site
+// share its links (the block operator reads each link once per n columns),
+// each link element is reused across the thread's R columns, and the R
+// columns of a neighbour are one contiguous run.
+template <typename T, int R>
 __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ links,
                                                 const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out,
                                                 const cplx<T>* __restrict__ aux, T a, T b, Geom g,
-                                                int n, FastDiv dn, int par, int sbl,
+                                                int n, FastDiv dgrp, int par, int sbl,
                                                 const int* __restrict__ skip) {
   using C = cplx<T>;
   if (skip && *skip) return;
+  const uint32_t ngrp = dgrp.d;  // n / R column groups per site
   uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
-  if (tid >= (uint32_t)g.vh * (uint32_t)n) return;
-  uint32_t s = fdiv(tid, dn);
-  int j = (int)(tid - s * (uint32_t)n);
+  if (tid >= (uint32_t)g.vh * ngrp) return;
+  uint32_t s = fdiv(tid, dgrp);
+  int j0 = (int)(tid - s * ngrp) * R;
   SiteCoord c = site_coords(s, g, par);
-  C acc0 = czero<C>(), acc1 = czero<C>(), acc2 = czero<C>();
+  C acc[3][R];
 #pragma unroll
+  for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
+  const size_t st = (size_t)1 << sbl;
+#pragma unroll 2
   for (int k = 0; k < 8; ++k) {
     int mu = k & 3;
     int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
-    const C* src = in + (size_t)nb * 3 * n + j;
-    C v0 = src[0], v1 = src[n], v2 = src[2 * n];
+    const C* src = in + (size_t)nb * 3 * n + j0;
     const C* L = links + link_off(s, k, 0, sbl);
-    const size_t st = (size_t)1 << sbl;
-    acc0 = cfma(L[0 * st], v0, acc0);
-    acc0 = cfma(L[1 * st], v1, acc0);
-    acc0 = cfma(L[2 * st], v2, acc0);
-    acc1 = cfma(L[3 * st], v0, acc1);
-    acc1 = cfma(L[4 * st], v1, acc1);
-    acc1 = cfma(L[5 * st], v2, acc1);
-    acc2 = cfma(L[6 * st], v0, acc2);
-    acc2 = cfma(L[7 * st], v1, acc2);
-    acc2 = cfma(L[8 * st], v2, acc2);
+    C l[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) l[e] = L[e * st];
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb) {
+      C v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[cb * n + r];
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[r], acc[a3][r]);
+    }
   }
-  size_t o = (size_t)s * 3 * n + j;
-  if (aux) {
-    out[o] = cadd(cscale(aux[o], a), cscale(acc0, b));
-    out[o + n] = cadd(cscale(aux[o + n], a), cscale(acc1, b));
-    out[o + 2 * n] = cadd(cscale(aux[o + 2 * n], a), cscale(acc2, b));
-  } else {
-    out[o] = cscale(acc0, b);
-    out[o + n] = cscale(acc1, b);
-    out[o + 2 * n] = cscale(acc2, b);
-  }
+  size_t o = (size_t)s * 3 * n + j0;
+#pragma unroll
+  for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      size_t oo = o + a3 * n + r;
+      out[oo] = aux ? cadd(cscale(aux[oo], a), cscale(acc[a3][r], b)) : cscale(acc[a3][r], b);
+    }
 }
 
 }  // namespace
@@ -119,10 +126,22 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   const DevBuf& lb = sizeof(T) == 8 ? c->links64 : c->links32;
   size_t pstride = (size_t)c->nblk * 72 << c->sbl;
   const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
-  uint32_t nthr = (uint32_t)c->vh * (uint32_t)n;
-  k_hop<T><<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(
-      links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom, n,
-      make_fastdiv(n), par, c->sbl, skip);
+  const int R = (n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1);
+  uint32_t ngrp = (uint32_t)(n / R);
+  uint32_t nthr = (uint32_t)c->vh * ngrp;
+  dim3 grid((nthr + BMS_WG - 1) / BMS_WG);
+  FastDiv dg = make_fastdiv(ngrp);
+#define HOP_LAUNCH(RR)                                                                     \
+  k_hop<T, RR><<<grid, BMS_WG, 0, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out,    \
+                                              (const cplx<T>*)aux, (T)a, (T)b, c->geom, n, \
+                                              dg, par, c->sbl, skip)
+  if (R == 4)
+    HOP_LAUNCH(4);
+  else if (R == 2)
+    HOP_LAUNCH(2);
+  else
+    HOP_LAUNCH(1);
+#undef HOP_LAUNCH
   return hipGetLastError();
 }
 

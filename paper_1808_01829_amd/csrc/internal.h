@@ -19,6 +19,8 @@ struct SolverFlags {
   int halted;     // the update kernel skips too (set one step after stop)
   int error;      // 0 or a BMS_E* code raised on the device
   int iter;       // completed block iterations
+  int need_explicit;  // V^H V must come from the explicit Gram this iteration
+  int rel_skip;       // the last reliable update kept the iterated residual
   int active[BMS_MAX_SHIFTS];  // shift still updated
   int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
   double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift
@@ -40,6 +42,8 @@ struct bms_ctx {
   DevBuf links64, links32;  // [parity][blocked links] complex
   std::vector<DevBuf> scratch;  // named by slot index
   std::string last_error;
+  // kernel variants (bms_autotune); -1 = built-in default
+  int update_variant = -1;
   // per-kernel timing (bms_timing_enable)
   bool timing = false;
   double kt_ms[BMS_NKERNELS] = {0};

@@ -189,6 +189,7 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
     fl->halted = 0;
     fl->error = 0;
     fl->iter = 0;
+    fl->need_explicit = 0;
     *s.counter = 0;
   }
   if (pass == 0)
@@ -231,12 +232,116 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
   }
 }
 
-// Per iteration, after G_k = P^H (A + s0) P: alpha_k and every active shift's
-// beta^(s)_k, alpha^(s)_k. Block s handles shift s (sorted; s = 0 is s0).
+// Reliable update of the unshifted system: the true FP64 residual R0 =
+// B - (A + s0) X^(0) replaces the iterated one, R0 = Q delta with the
+// Cholesky-QR factor delta = chol(R0^H R0)^H.
+__global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallState s,
+                                                           SolverFlags* fl, const double2* Gin,
+                                                           double2* Rinv_out) {
+  __shared__ double2 L0[NN], L1[NN], L2[NN];
+  const int n = p.n;
+  if (fl->stop) {
+    if (threadIdx.x == 0) fl->rel_skip = 1;
+    return;
+  }
+  sm_load(L0, Gin, n);
+  int st = sm_chol_upper(L1, L0, n, p.breakdown_tol);
+  if (st) {
+    // columns of the true residual too unequal to factor: keep the iterated one
+    if (threadIdx.x == 0) fl->rel_skip = 1;
+    if (st == BMS_ENAN) raise_error(fl, st);
+    return;
+  }
+  sm_triinv_upper(L2, L1, n);
+  sm_store(Rinv_out, L2, n);
+  sm_store(s.delta, L1, n);
+  if (threadIdx.x == 0) fl->rel_skip = 0;
+}
+
+// Completion of one iteration's small step: count this block's arrival and
+// whether its shift met tol; the last block to arrive stops the solve when
+// all did, logs the active count and advances the iteration counter.
+__device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFlags* fl,
+                             int done) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    int v = atomicAdd(s.counter, 1 + (done << 16)) + 1 + (done << 16);
+    if ((v & 0xffff) == p.ns) {
+      __threadfence();
+      if ((v >> 16) == p.ns || fl->error) fl->stop = 1;
+      int na = 1;
+      for (int i = 1; i < p.ns; ++i) na += fl->active[i];
+      if (s.nact_log && fl->iter < p.max_iter) s.nact_log[fl->iter] = na;
+      fl->need_explicit = 0;
+      fl->iter = fl->iter + 1;
+      atomicExch(s.counter, 0);
+    }
+  }
+}
+
+// Everything that needs rho_k (in R, LDS): rho_k^-1, delta_k, the shift's
+// residual coefficients delta^(s)_k = rho_k alpha_k^-1 alpha^(s)_k, its update
+// matrix Mp and its convergence. Gk = G_k = alpha_k^-1 (LDS copy).
 template <typename T>
-__global__ __launch_bounds__(BMS_WG) void k_small_alpha(SmallParams p, SmallState s,
-                                                        SolverFlags* fl, cplx<T>* Mx) {
-  __shared__ double2 L0[NN], L1[NN], L2[NN], L3[NN], L4[NN];
+__device__ void rho_part(const SmallParams& p, const SmallState& s, SolverFlags* fl, cplx<T>* Mp,
+                         const double2* R, const double2* Gk, double2* T0, double2* T1,
+                         double2* D, int q, int cur) {
+  __shared__ double colmax;
+  const int n = p.n, nn = n * n;
+  if (q == 0) {
+    sm_triinv_upper(T0, R, n);
+    sm_store(s.rhoinv, T0, n);
+    sm_store(s.rhob + cur * nn, R, n);
+    sm_load(T1, s.delta, n);
+    sm_mm(D, R, 0, T1, 0, n);  // delta_k = rho_k delta_{k-1}
+    sm_store(s.delta, D, n);
+    for (int e = threadIdx.x; e < nn; e += BMS_WG) {
+      int i = e / n, j = e - (e / n) * n;
+      Mp[e] = from_d<cplx<T>>(cconj(R[j * n + i]));  // rho_k^dag
+    }
+  } else {
+    sm_mm(T0, R, 0, Gk, 0, n);  // rho_k alpha_k^-1
+    sm_load(T1, s.alpha_s + (size_t)q * nn, n);
+    sm_mm(D, T0, 0, T1, 0, n);  // delta^(s)_k
+    sm_load(T1, s.beta_s + (size_t)q * nn, n);
+    sm_mm(T0, T1, 0, R, 1, n);  // beta^(s)_k rho_k^dag
+    sm_store_t(Mp + (size_t)q * nn, T0, n);
+  }
+  // relative residual estimate: max_i |delta^(s) e_i| / |b_i|
+  if (threadIdx.x == 0) {
+    double m = 0;
+    for (int i = 0; i < n; ++i) {
+      double c = 0;
+      for (int k = 0; k < n; ++k) c += cabs2(D[k * n + i]);
+      double r = sqrt(c) / s.norm0[i];
+      if (!(r == r)) r = 1e300;
+      m = r > m ? r : m;
+    }
+    colmax = m;
+  }
+  __syncthreads();
+  double r = colmax;
+  if (threadIdx.x == 0) {
+    fl->res[q] = r;
+    if (q > 0) fl->conv[q] = r < p.freeze_tol;
+    if (r >= 1e300) {
+      atomicCAS(&fl->error, 0, BMS_ENAN);
+      fl->halted = 1;
+    }
+  }
+  finish_shift(p, s, fl, r < p.tol);
+}
+
+// One iteration's n x n work, after G4 = [P^H W, Q^H W, W^H W, Q^H Q]:
+//   alpha_k = (P^H W)^-1; beta^(s)_k, alpha^(s)_k (Algorithm 1, lines 10-11);
+//   V^H V from the expansion, rho_k = chol(V^H V)^H; then rho_part.
+// If that Cholesky loses its pivot, need_explicit is raised and the explicit
+// Gram of V plus k_small_rho_explicit finish the iteration instead.
+template <typename T>
+__global__ __launch_bounds__(BMS_WG) void k_small_iter(SmallParams p, SmallState s,
+                                                       SolverFlags* fl, cplx<T>* Mx,
+                                                       cplx<T>* Mp) {
+  __shared__ double2 Gk[NN], A[NN], R[NN], T0[NN], T1[NN], T2[NN], T3[NN];
   const int n = p.n, nn = n * n;
   const int q = blockIdx.x;
   if (fl->stop || fl->iter >= p.max_iter) {
@@ -247,140 +352,116 @@ __global__ __launch_bounds__(BMS_WG) void k_small_alpha(SmallParams p, SmallStat
     return;
   }
   const int cur = fl->iter & 1, prev = cur ^ 1;
-  if (q > 0 && fl->conv[q]) {
+  if (q > 0 && (fl->conv[q] || !fl->active[q])) {
     if (threadIdx.x == 0) fl->active[q] = 0;
-    if (q > 0) return;
-  }
-  if (q > 0 && !fl->active[q]) return;
-  sm_load(L0, s.Ggram, n);
-  int st = sm_chol_upper(L1, L0, n, 0.0);
-  if (st) {
-    if (q == 0) raise_error(fl, st == BMS_EBREAKDOWN ? BMS_EBREAKDOWN : BMS_ENAN);
+    finish_shift(p, s, fl, 1);
     return;
   }
-  sm_triinv_upper(L2, L1, n);
-  sm_mm(L3, L2, 0, L2, 1, n);  // alpha = R^-1 R^-H = G^-1
+  sm_load(Gk, s.G4, n);
+  int st = sm_chol_upper(T0, Gk, n, 0.0);
+  if (st) {
+    if (q == 0) raise_error(fl, st);
+    return;
+  }
+  sm_triinv_upper(T1, T0, n);
+  sm_mm(A, T1, 0, T1, 1, n);  // alpha_k = R^-1 R^-H = G_k^-1
   if (q == 0) {
-    sm_store(s.alpha, L3, n);
-    sm_store(s.Gb + cur * nn, L0, n);
-    sm_load(L1, s.delta, n);
-    sm_mm(L2, L3, 0, L1, 0, n);  // alpha^(0)_k = alpha_k delta_{k-1}
-    sm_store(s.alpha_s, L2, n);
-    sm_store_t(Mx, L2, n);
-    return;
-  }
-  const double dsig = p.sigma[q] - p.sigma[0];
-  sm_load(L1, s.rhob + prev * nn, n);
-  sm_mm(L2, L3, 0, L1, 0, n);  // alpha_k rho_{k-1}
-  sm_load(L1, s.Gb + prev * nn, n);
-  sm_mm(L0, L2, 0, L1, 0, n);  // t = alpha_k rho_{k-1} alpha_{k-1}^-1
-  const double2* bold = s.beta_s + (size_t)q * nn;
-  for (int e = threadIdx.x; e < nn; e += BMS_WG) {
-    int i = e / n, j = e - (e / n) * n;
-    L1[e] = csub(make_double2(i == j ? 1.0 : 0.0, 0), bold[e]);
-  }
-  __syncthreads();
-  sm_mm(L2, L0, 0, L1, 0, n);  // t (1 - beta_{k-1})
-  sm_load(L1, s.rhob + prev * nn, n);
-  sm_mm(L4, L2, 0, L1, 1, n);  // ... rho_{k-1}^dag
-  for (int e = threadIdx.x; e < nn; e += BMS_WG) {
-    int i = e / n, j = e - (e / n) * n;
-    double2 v = cadd(L4[e], cscale(L3[e], dsig));
-    if (i == j) v.x += 1.0;
-    L4[e] = v;
-  }
-  __syncthreads();
-  st = sm_inv_general(L2, L4, n);  // beta^(s)_k
-  if (st) {
-    raise_error(fl, BMS_ENAN);
-    return;
-  }
-  sm_mm(L4, L2, 0, L0, 0, n);  // beta t
-  sm_load(L1, s.alpha_s + (size_t)q * nn, n);
-  sm_mm(L0, L4, 0, L1, 0, n);  // alpha^(s)_k = beta t alpha^(s)_{k-1}
-  sm_store(s.beta_s + (size_t)q * nn, L2, n);
-  sm_store(s.alpha_s + (size_t)q * nn, L0, n);
-  sm_store_t(Mx + (size_t)q * nn, L0, n);
-}
-
-// Per iteration, after G = V^H V with V = Q_{k-1} - W alpha_k: rho_k, rho_k^-1,
-// delta_k, the update matrices Mp[s] = beta^(s)_k rho_k^dag, and convergence.
-template <typename T>
-__global__ __launch_bounds__(BMS_WG) void k_small_rho(SmallParams p, SmallState s,
-                                                      SolverFlags* fl, cplx<T>* Mp) {
-  __shared__ double2 L0[NN], L1[NN], L2[NN], L3[NN];
-  __shared__ double colmax;
-  const int n = p.n, nn = n * n;
-  const int q = blockIdx.x;
-  if (fl->stop) return;
-  const int cur = fl->iter & 1;
-  const bool act = (q == 0) || fl->active[q];
-  int done = 1;
-  if (act) {
-    sm_load(L0, s.Gqr, n);
-    int st = sm_chol_upper(L1, L0, n, p.breakdown_tol);
-    if (st) {
-      if (q == 0) raise_error(fl, st);
-      return;
-    }
-    if (q == 0) {
-      sm_triinv_upper(L2, L1, n);
-      sm_store(s.rhoinv, L2, n);
-      sm_store(s.rhob + cur * nn, L1, n);
-      sm_load(L0, s.delta, n);
-      sm_mm(L3, L1, 0, L0, 0, n);  // delta_k = rho_k delta_{k-1}
-      sm_store(s.delta, L3, n);
-      for (int e = threadIdx.x; e < nn; e += BMS_WG) {
-        int i = e / n, j = e - (e / n) * n;
-        Mp[e] = from_d<cplx<T>>(cconj(L1[j * n + i]));  // rho_k^dag
-      }
-    } else {
-      sm_load(L0, s.Gb + cur * nn, n);
-      sm_mm(L2, L1, 0, L0, 0, n);  // rho_k alpha_k^-1
-      sm_load(L0, s.alpha_s + (size_t)q * nn, n);
-      sm_mm(L3, L2, 0, L0, 0, n);  // delta^(s)_k
-      sm_load(L0, s.beta_s + (size_t)q * nn, n);
-      sm_mm(L2, L0, 0, L1, 1, n);  // beta^(s)_k rho_k^dag
-      sm_store_t(Mp + (size_t)q * nn, L2, n);
-    }
-    // relative residual estimate: max_i |delta^(s) e_i| / |b_i|
-    if (threadIdx.x == 0) {
-      double m = 0;
-      for (int i = 0; i < n; ++i) {
-        double c = 0;
-        for (int k = 0; k < n; ++k) c += cabs2(L3[k * n + i]);
-        double r = sqrt(c) / s.norm0[i];
-        if (!(r == r)) r = 1e300;
-        m = r > m ? r : m;
-      }
-      colmax = m;
+    sm_store(s.alpha, A, n);
+    sm_store(s.Gb + cur * nn, Gk, n);
+    sm_load(T1, s.delta, n);
+    sm_mm(T0, A, 0, T1, 0, n);  // alpha^(0)_k = alpha_k delta_{k-1}
+    sm_store(s.alpha_s, T0, n);
+    sm_store_t(Mx, T0, n);
+  } else {
+    const double dsig = p.sigma[q] - p.sigma[0];
+    sm_load(T1, s.rhob + prev * nn, n);
+    sm_mm(T2, A, 0, T1, 0, n);  // alpha_k rho_{k-1}
+    sm_load(T1, s.Gb + prev * nn, n);
+    sm_mm(T0, T2, 0, T1, 0, n);  // t = alpha_k rho_{k-1} alpha_{k-1}^-1
+    const double2* bold = s.beta_s + (size_t)q * nn;
+    for (int e = threadIdx.x; e < nn; e += BMS_WG) {
+      int i = e / n, j = e - (e / n) * n;
+      T1[e] = csub(make_double2(i == j ? 1.0 : 0.0, 0), bold[e]);
     }
     __syncthreads();
-    double r = colmax;
-    if (threadIdx.x == 0) {
-      fl->res[q] = r;
-      if (q > 0) fl->conv[q] = r < p.freeze_tol;
-      if (r >= 1e300) {
-        atomicCAS(&fl->error, 0, BMS_ENAN);
-        fl->halted = 1;
-      }
+    sm_mm(T2, T0, 0, T1, 0, n);  // t (1 - beta_{k-1})
+    sm_load(T1, s.rhob + prev * nn, n);
+    sm_mm(T3, T2, 0, T1, 1, n);  // ... rho_{k-1}^dag
+    for (int e = threadIdx.x; e < nn; e += BMS_WG) {
+      int i = e / n, j = e - (e / n) * n;
+      double2 v = cadd(T3[e], cscale(A[e], dsig));
+      if (i == j) v.x += 1.0;
+      T3[e] = v;
     }
-    done = r < p.tol;
+    __syncthreads();
+    st = sm_inv_general(T2, T3, n);  // beta^(s)_k
+    if (st) {
+      raise_error(fl, BMS_ENAN);
+      return;
+    }
+    sm_mm(T3, T2, 0, T0, 0, n);  // beta t
+    sm_load(T1, s.alpha_s + (size_t)q * nn, n);
+    sm_mm(T0, T3, 0, T1, 0, n);  // alpha^(s)_k = beta t alpha^(s)_{k-1}
+    sm_store(s.beta_s + (size_t)q * nn, T2, n);
+    sm_store(s.alpha_s + (size_t)q * nn, T0, n);
+    sm_store_t(Mx + (size_t)q * nn, T0, n);
+    __syncthreads();
   }
-  // grid completion: count arrivals (low 16 bits) and converged shifts (high)
+  // V^H V = QQ - QW A - A^H QW^H + A^H WW A
+  sm_load(T1, s.G4 + nn, n);       // Q^H W
+  sm_mm(T0, T1, 0, A, 0, n);       // QW A
+  sm_load(T2, s.G4 + 2 * nn, n);   // W^H W
+  sm_mm(T3, T2, 0, A, 0, n);       // WW A
+  sm_mm(T2, A, 1, T3, 0, n);       // A^H WW A
+  const double2* QQ = s.G4 + 3 * nn;
+  for (int e = threadIdx.x; e < nn; e += BMS_WG) {
+    int i = e / n, j = e - (e / n) * n;
+    // (QW A)^H = A^H QW^H
+    T3[e] = cadd(csub(csub(QQ[e], T0[e]), cconj(T0[j * n + i])), T2[e]);
+  }
+  __syncthreads();
+  // The expansion cancels when V is small next to Q (|V|^2 / |Q|^2 ~ rounding
+  // relative to the result); then the explicit Gram of V is used instead.
+  __shared__ int cancel;
   if (threadIdx.x == 0) {
-    __threadfence();
-    int v = atomicAdd(s.counter, 1 + (done << 16)) + 1 + (done << 16);
-    if ((v & 0xffff) == p.ns) {
-      __threadfence();
-      if ((v >> 16) == p.ns || fl->error) fl->stop = 1;
-      int na = 1;
-      for (int i = 1; i < p.ns; ++i) na += fl->active[i];
-      if (s.nact_log && fl->iter < p.max_iter) s.nact_log[fl->iter] = na;
-      fl->iter = fl->iter + 1;
-      atomicExch(s.counter, 0);
+    double tv = 0, tq = 0;
+    for (int i = 0; i < n; ++i) {
+      tv += T3[i * n + i].x;
+      tq += QQ[i * n + i].x;
     }
+    cancel = !(tv >= 1e-4 * tq);
   }
+  __syncthreads();
+  st = cancel ? BMS_EBREAKDOWN : sm_chol_upper(R, T3, n, p.breakdown_tol);
+  if (st) {
+    if (st == BMS_ENAN) {
+      if (q == 0) raise_error(fl, st);
+    } else if (q == 0 && threadIdx.x == 0) {
+      fl->need_explicit = 1;  // the explicit Gram finishes this iteration
+    }
+    return;
+  }
+  rho_part<T>(p, s, fl, Mp, R, Gk, T0, T1, T2, q, cur);
+}
+
+// Fallback when the expansion lost accuracy: rho_k from the explicit V^H V.
+template <typename T>
+__global__ __launch_bounds__(BMS_WG) void k_small_rho_explicit(SmallParams p, SmallState s,
+                                                               SolverFlags* fl, cplx<T>* Mp) {
+  __shared__ double2 Gk[NN], R[NN], T0[NN], T1[NN], T2[NN];
+  const int n = p.n;
+  const int q = blockIdx.x;
+  if (fl->stop || !fl->need_explicit) return;
+  if (q > 0 && !fl->active[q]) return;  // already counted by k_small_iter
+  const int cur = fl->iter & 1;
+  sm_load(T0, s.Gqr, n);
+  int st = sm_chol_upper(R, T0, n, p.breakdown_tol);
+  if (st) {
+    if (q == 0) raise_error(fl, st);
+    return;
+  }
+  sm_load(Gk, s.G4, n);
+  rho_part<T>(p, s, fl, Mp, R, Gk, T0, T1, T2, q, cur);
 }
 
 }  // namespace
@@ -397,25 +478,30 @@ hipError_t launch_small_init_pass2(hipStream_t st, const SmallParams& p, SmallSt
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_small_alpha(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                              cplx<T>* Mx) {
-  k_small_alpha<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mx);
+hipError_t launch_small_reliable(hipStream_t st, const SmallParams& p, SmallState s,
+                                 SolverFlags* fl, const double2* Gin, double2* Rinv_out) {
+  k_small_reliable<<<1, BMS_WG, 0, st>>>(p, s, fl, Gin, Rinv_out);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_small_rho(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                            cplx<T>* Mp) {
-  k_small_rho<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mp);
+hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
+                             cplx<T>* Mx, cplx<T>* Mp) {
+  k_small_iter<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mx, Mp);
   return hipGetLastError();
 }
 
-template hipError_t launch_small_alpha<double>(hipStream_t, const SmallParams&, SmallState,
-                                               SolverFlags*, double2*);
-template hipError_t launch_small_alpha<float>(hipStream_t, const SmallParams&, SmallState,
-                                              SolverFlags*, float2*);
-template hipError_t launch_small_rho<double>(hipStream_t, const SmallParams&, SmallState,
-                                             SolverFlags*, double2*);
-template hipError_t launch_small_rho<float>(hipStream_t, const SmallParams&, SmallState,
-                                            SolverFlags*, float2*);
+template <typename T>
+hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
+                                     SolverFlags* fl, cplx<T>* Mp) {
+  k_small_rho_explicit<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mp);
+  return hipGetLastError();
+}
+
+#define INST_SMALL(T, C)                                                                    \
+  template hipError_t launch_small_iter<T>(hipStream_t, const SmallParams&, SmallState,     \
+                                           SolverFlags*, C*, C*);                           \
+  template hipError_t launch_small_rho_explicit<T>(hipStream_t, const SmallParams&,         \
+                                                   SmallState, SolverFlags*, C*);
+INST_SMALL(double, double2)
+INST_SMALL(float, float2)

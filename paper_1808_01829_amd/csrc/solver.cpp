@@ -2,14 +2,22 @@
 //
 // Per iteration the device runs
 //   hop D_oe P^(0) -> W1;  hop D_eo W1 -> W = (m^2 + s0) P^(0) - D_eo W1
-//   G_k = P^(0)H W                          (Gram, FP64)
-//   alpha_k, beta^(s)_k, alpha^(s)_k        (small kernel, one WG per shift)
-//   G_V = V^H V, V = Q_{k-1} - W alpha_k    (Cholesky-QR Gram, FP64)
-//   rho_k, delta_k, delta^(s)_k, Mp[s]       (small kernel, convergence)
-//   Q_k, X^(s), P^(s) for all active shifts (fused update)
-// The host only enqueues chunks of iterations (optionally as a captured
-// hipGraph) and reads a small flag block between chunks; stopping, freezing
-// of converged shifts and the iteration limit are decided on the device.
+//   G4 = [P^H W, Q^H W, W^H W, Q^H Q]        (one pass, FP64)
+//   alpha_k, beta^(s)_k, alpha^(s)_k, rho_k, delta^(s)_k, convergence
+//                                            (one work-group per shift)
+//   [explicit V^H V and rho_k, only if the expansion lost its pivot]
+//   Q_k, X^(s), P^(s) for all active shifts  (fused update)
+// The host only enqueues chunks of iterations and reads a small flag block
+// between chunks; stopping, freezing of converged shifts and the iteration
+// limit are decided on the device.
+//
+// Precision control. In BMS_PREC_MIXED the block vectors and the operator
+// are FP32 (the n x n algebra stays FP64): every reliable_interval iterations
+// the FP32 increments of every X^(s) are added into FP64 solutions and the
+// unshifted residual is replaced by the true FP64 one (re-factored by
+// Cholesky-QR). In both precisions, after the main solve every shift whose
+// true FP64 residual misses tol is refined by defect correction: its residual
+// block, column-normalised, is solved for with the same solver and added back.
 #include <string.h>
 
 #include <algorithm>
@@ -33,11 +41,26 @@ enum Slot {
   S_M,
   S_FLAGS,
   S_RES,
-  S_X64,
-  S_B32,
   S_LOG,
+  S_R1,    // FP64 odd temporary
+  S_R2,    // FP64 even temporary
+  S_R0,    // FP64 true residual (reliable update)
+  S_RB,    // FP64 defect-correction right-hand side
+  S_E,     // FP64 defect-correction solution
+  S_COLS,  // per-column scale factors
+  S_RBC,   // one column of S_RB
+  S_EC,    // its correction
   S_COUNT
 };
+
+const double kEps = 2.220446049250313e-16;
+const size_t kFlagsBytes = sizeof(SolverFlags) + 4 * CNT_STRIDE * sizeof(int) + 64;
+
+// partial sums of a grid reduction over nb blocks of P entries, plus the
+// first-level group sums
+size_t part_bytes(int nb, int P) {
+  return ((size_t)nb + (nb + RED_GROUP - 1) / RED_GROUP) * P * sizeof(double2) + 64;
+}
 
 struct Work {
   int rows, n, ns;
@@ -46,8 +69,9 @@ struct Work {
   SmallState sm;
   SolverFlags* flags;
   double2* partials;
-  int* counters;  // [0] gram, [1] cholqr gram, [2] residual / misc
+  int* counters;  // sets of CNT_STRIDE: [0] Grams, [1] Cholesky-QR Gram, [2] misc, [3] small
   double2* Rinv;
+  double2* Gtmp;
   int nb;
 };
 
@@ -65,7 +89,7 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   if ((rc = scratch_buf(c, S_P, w.blk * es * ns, &w.P))) return rc;
   if ((rc = scratch_buf(c, S_X, w.blk * es * ns, &w.X))) return rc;
   size_t nn = (size_t)n * n;
-  size_t small_elems = 2 * nn + 2 * nn + 5 * nn + 2 * ns * nn + 2 * nn + n;
+  size_t small_elems = 2 * nn + 2 * nn + 8 * nn + 2 * ns * nn + 3 * nn + n;
   void* sp;
   if ((rc = scratch_buf(c, S_SMALL, small_elems * sizeof(double2) + 64, &sp))) return rc;
   double2* d = (double2*)sp;
@@ -79,8 +103,8 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   d += nn;
   w.sm.delta = d;
   d += nn;
-  w.sm.Ggram = d;
-  d += nn;
+  w.sm.G4 = d;
+  d += 4 * nn;
   w.sm.Gqr = d;
   d += nn;
   w.sm.beta_s = d;
@@ -91,32 +115,30 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   d += nn;
   w.Rinv = d;
   d += nn;
+  w.Gtmp = d;
+  d += nn;
   w.sm.norm0 = (double*)d;
   w.nb = gram_blocks(w.rows, n);
   void* pp;
-  if ((rc = scratch_buf(c, S_PART, (size_t)w.nb * nn * sizeof(double2) + 64, &pp))) return rc;
+  if ((rc = scratch_buf(c, S_PART, part_bytes(w.nb, 4 * nn), &pp))) return rc;
   w.partials = (double2*)pp;
   void* mp;
   if ((rc = scratch_buf(c, S_M, 2 * ns * nn * es, &mp))) return rc;
   w.Mx = mp;
   w.Mp = (char*)mp + ns * nn * es;
   void* fp;
-  if ((rc = scratch_buf(c, S_FLAGS, sizeof(SolverFlags) + 64, &fp))) return rc;
+  if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
   w.flags = (SolverFlags*)fp;
   w.counters = (int*)((char*)fp + sizeof(SolverFlags));
-  w.sm.counter = w.counters + 3;
+  w.sm.counter = w.counters + 3 * CNT_STRIDE;
   void* lp;
   if ((rc = scratch_buf(c, S_LOG, (size_t)max_iter * sizeof(int) + 64, &lp))) return rc;
   w.sm.nact_log = (int*)lp;
   return BMS_OK;
 }
 
-struct HostFlags {
-  SolverFlags f;
-};
-
 // kernel classes of the 7 launches of one iteration (timing)
-const int kIterKernel[7] = {BMS_KERNEL_HOP,   BMS_KERNEL_HOP,    BMS_KERNEL_GRAM,  BMS_KERNEL_SMALL,
+const int kIterKernel[7] = {BMS_KERNEL_HOP,   BMS_KERNEL_HOP,   BMS_KERNEL_GRAM,  BMS_KERNEL_SMALL,
                             BMS_KERNEL_CHOLQR, BMS_KERNEL_SMALL, BMS_KERNEL_UPDATE};
 
 template <typename T>
@@ -131,15 +153,18 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   MARK(1);
   HIP_TRY(c, launch_hop<T>(c, 0, w.n, w.W1, w.W, P0, mass * mass + sp.sigma[0], -1.0, skip));
   MARK(2);
-  HIP_TRY(c, launch_gram<T>(c->stream, w.rows, w.n, P0, w.W, w.sm.Ggram, w.partials,
-                            w.counters + 0, w.nb, skip));
+  HIP_TRY(c, launch_gram4<T>(c->stream, w.rows, w.n, P0, w.Q, w.W, w.sm.G4, w.partials,
+                             w.counters, w.nb, skip));
   MARK(3);
-  HIP_TRY(c, launch_small_alpha<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mx));
+  HIP_TRY(c, launch_small_iter<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mx,
+                                  (cplx<T>*)w.Mp));
   MARK(4);
+  // explicit Cholesky-QR Gram, only when the expansion lost its pivot
   HIP_TRY(c, launch_cholqr_gram<T>(c->stream, w.rows, w.n, w.Q, w.W, w.sm.alpha, w.sm.Gqr,
-                                   w.partials, w.counters + 1, w.nb, skip));
+                                   w.partials, w.counters + CNT_STRIDE, w.nb,
+                                   &w.flags->need_explicit));
   MARK(5);
-  HIP_TRY(c, launch_small_rho<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mp));
+  HIP_TRY(c, launch_small_rho_explicit<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mp));
   MARK(6);
   UpdateArgs<T, T> ua;
   ua.rows = w.rows;
@@ -155,7 +180,8 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   ua.Mp = (const cplx<T>*)w.Mp;
   ua.flags = w.flags;
   for (int s = 0; s < BMS_MAX_SHIFTS; ++s) ua.xidx[s] = s < w.ns ? s : 0;
-  HIP_TRY(c, (launch_update<T, T>(c->stream, ua)));
+  // built-in default: four row chunks, one coefficient column at a time
+  HIP_TRY(c, (launch_update_fast<T, T>(c->stream, ua, c->update_variant < 0 ? 2 : c->update_variant)));
   MARK(7);
 #undef MARK
   return BMS_OK;
@@ -166,15 +192,15 @@ template <typename T>
 int enqueue_setup(bms_ctx* c, const Work& w, const SmallParams& sp, const void* B) {
   size_t es = sizeof(cplx<T>);
   // grid-completion counters must start at zero (they are left at zero after use)
-  HIP_TRY(c, launch_fill_zero(c->stream, w.counters, 64));
+  HIP_TRY(c, launch_fill_zero(c->stream, w.counters, 4 * CNT_STRIDE * sizeof(int)));
   HIP_TRY(c, launch_fill_zero(c->stream, w.X, w.blk * es * w.ns));
-  HIP_TRY(c, launch_gram<T>(c->stream, w.rows, w.n, B, B, w.sm.Ggram, w.partials, w.counters + 0,
+  HIP_TRY(c, launch_gram<double>(c->stream, w.rows, w.n, B, B, w.sm.G4, w.partials, w.counters,
+                                 w.nb, nullptr));
+  HIP_TRY(c, launch_small_init(c->stream, sp, w.sm, w.flags, w.sm.G4, w.Rinv));
+  HIP_TRY(c, launch_block_matmul_d<T>(c->stream, w.rows, w.n, B, w.Rinv, w.W, nullptr));
+  HIP_TRY(c, launch_gram<T>(c->stream, w.rows, w.n, w.W, w.W, w.sm.G4, w.partials, w.counters,
                             w.nb, nullptr));
-  HIP_TRY(c, launch_small_init(c->stream, sp, w.sm, w.flags, w.sm.Ggram, w.Rinv));
-  HIP_TRY(c, launch_block_matmul<T>(c->stream, w.rows, w.n, B, w.Rinv, w.W));
-  HIP_TRY(c, launch_gram<T>(c->stream, w.rows, w.n, w.W, w.W, w.sm.Ggram, w.partials,
-                            w.counters + 0, w.nb, nullptr));
-  HIP_TRY(c, launch_small_init_pass2(c->stream, sp, w.sm, w.flags, w.sm.Ggram, w.Rinv));
+  HIP_TRY(c, launch_small_init_pass2(c->stream, sp, w.sm, w.flags, w.sm.G4, w.Rinv));
   HIP_TRY(c, launch_block_matmul<T>(c->stream, w.rows, w.n, w.W, w.Rinv, w.Q));
   for (int s = 0; s < w.ns; ++s)
     HIP_TRY(c, hipMemcpyAsync((char*)w.P + s * w.blk * es, w.Q, w.blk * es,
@@ -182,26 +208,155 @@ int enqueue_setup(bms_ctx* c, const Work& w, const SmallParams& sp, const void* 
   return BMS_OK;
 }
 
-__attribute__((unused)) static int map_device_error(int e) { return e; }
+// MIXED: FP32 increments into the FP64 solutions, then the unshifted true
+// residual replaces the iterated one.
+int enqueue_reliable(bms_ctx* c, const Work& w, const SmallParams& sp, double mass, const void* B,
+                     void* Xout, const int* xmap, void* R1, void* R2, void* R0, bool flush_only) {
+  const int* skip = &w.flags->stop;
+  HIP_TRY(c, launch_flush(c->stream, w.rows, w.n, w.ns, w.X, Xout, xmap,
+                          flush_only ? nullptr : skip));
+  if (flush_only) return BMS_OK;
+  const double2* X0 = (const double2*)Xout + (size_t)xmap[0] * w.blk;
+  HIP_TRY(c, launch_hop<double>(c, 1, w.n, X0, R1, nullptr, 0.0, 1.0, skip));
+  HIP_TRY(c, launch_hop<double>(c, 0, w.n, R1, R2, X0, mass * mass + sp.sigma[0], -1.0, skip));
+  HIP_TRY(c, launch_resid_block(c->stream, w.rows, w.n, B, R2, nullptr, nullptr, R0, skip));
+  HIP_TRY(c, launch_gram<double>(c->stream, w.rows, w.n, R0, R0, w.Gtmp, w.partials,
+                                 w.counters + 2 * CNT_STRIDE, w.nb, skip));
+  HIP_TRY(c, launch_small_reliable(c->stream, sp, w.sm, w.flags, w.Gtmp, w.Rinv));
+  HIP_TRY(c, launch_block_matmul_d<float>(c->stream, w.rows, w.n, R0, w.Rinv, w.Q,
+                                          &w.flags->rel_skip));
+  return BMS_OK;
+}
+
+struct CoreResult {
+  int iters = 0;
+  int error = 0;  // final failure (initial QR)
+  int soft = 0;   // the iteration stopped early on breakdown / non-finite values
+  int reliable = 0;
+};
+
+// One block multi-shift solve from X = 0. sigma[] ascending; the solution of
+// sigma[s] is written to Xout + xmap[s] * blk (FP64), which must not alias B.
+template <typename T>
+int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, const int* xmap,
+               double tol, int max_iter, const bms_opts& o, const void* B, void* Xout,
+               CoreResult& cr) {
+  int rc;
+  const bool mixed = sizeof(T) == 4;
+  SmallParams sp;
+  memset(&sp, 0, sizeof sp);
+  sp.n = n;
+  sp.ns = ns;
+  sp.max_iter = max_iter;
+  // The recurrence's residual estimate drifts from the true residual by
+  // rounding; stopping (and freezing) at tol/2 leaves that margin.
+  sp.tol = 0.5 * tol;
+  double ft = o.freeze_tol > 0 ? o.freeze_tol : sp.tol;
+  sp.freeze_tol = ft < sp.tol ? ft : sp.tol;
+  // a computed Gram resolves pivots only down to ~eps * trace
+  sp.breakdown_tol = 10.0 * n * kEps;
+  for (int s = 0; s < ns; ++s) sp.sigma[s] = sigma[s];
+  Work w;
+  if ((rc = alloc_work<T>(c, n, ns, max_iter, w))) return rc;
+  void *R1 = nullptr, *R2 = nullptr, *R0 = nullptr;
+  if (mixed) {
+    size_t b64 = w.blk * sizeof(double2);
+    if ((rc = scratch_buf(c, S_R1, b64, &R1))) return rc;
+    if ((rc = scratch_buf(c, S_R2, b64, &R2))) return rc;
+    if ((rc = scratch_buf(c, S_R0, b64, &R0))) return rc;
+    for (int s = 0; s < ns; ++s)
+      HIP_TRY(c, launch_fill_zero(c->stream, (double2*)Xout + (size_t)xmap[s] * w.blk,
+                                  w.blk * sizeof(double2)));
+  }
+  if ((rc = enqueue_setup<T>(c, w, sp, B))) return rc;
+  SolverFlags hf;
+  const int K = o.check_interval;
+  long enqueued = 0, last_rel = 0;
+  if (c->timing && (int)c->evpool.size() < 8 * K) {
+    size_t old = c->evpool.size();
+    c->evpool.resize(8 * K);
+    for (size_t i = old; i < c->evpool.size(); ++i) HIP_TRY(c, hipEventCreate(&c->evpool[i]));
+  }
+  while (true) {
+    for (int k = 0; k < K; ++k)
+      if ((rc = enqueue_iteration<T>(c, w, sp, mass, c->timing ? &c->evpool[8 * k] : nullptr)))
+        return rc;
+    if (mixed && enqueued + K - last_rel >= o.reliable_interval) {
+      if ((rc = enqueue_reliable(c, w, sp, mass, B, Xout, xmap, R1, R2, R0, false))) return rc;
+      last_rel = enqueued + K;
+      cr.reliable++;
+    }
+    HIP_TRY(c, hipMemcpyAsync(&hf, w.flags, sizeof hf, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->timing) {
+      double G = 72.0 * c->vol * sizeof(T);
+      double S = (double)w.blk * sizeof(cplx<T>);
+      // the explicit Cholesky-QR Gram (slot 4) normally exits at once: no bytes
+      const double kbytes[7] = {G + 2 * S, G + 3 * S, 3 * S, 0, 0, 0, 0};
+      for (int k = 0; k < K; ++k) {
+        if (enqueued + k >= hf.iter) break;  // launches after the stop did no work
+        for (int i = 0; i < 7; ++i) {
+          float ms = 0;
+          HIP_TRY(c, hipEventElapsedTime(&ms, c->evpool[8 * k + i], c->evpool[8 * k + i + 1]));
+          int kc = kIterKernel[i];
+          c->kt_ms[kc] += ms;
+          c->kt_launches[kc] += 1;
+          c->kt_bytes[kc] += kbytes[i];
+        }
+      }
+    }
+    enqueued += K;
+    if (hf.stop) break;
+    if (enqueued > (long)max_iter + 2L * K)  // the device stops itself at max_iter
+      return set_err(c, BMS_EHIP, "device iteration control did not stop (iter %d)", hf.iter);
+  }
+  if (c->timing && hf.iter > 0) {
+    std::vector<int> nact(hf.iter);
+    HIP_TRY(c, hipMemcpyAsync(nact.data(), w.sm.nact_log, hf.iter * sizeof(int),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double S = (double)w.blk * sizeof(cplx<T>);
+    for (int k = 0; k < hf.iter; ++k) c->kt_bytes[BMS_KERNEL_UPDATE] += (3.0 + 4.0 * nact[k]) * S;
+  }
+  if (mixed) {
+    if ((rc = enqueue_reliable(c, w, sp, mass, B, Xout, xmap, R1, R2, R0, true))) return rc;
+  } else {
+    size_t bytes = w.blk * sizeof(double2);
+    for (int s = 0; s < ns; ++s)
+      HIP_TRY(c, hipMemcpyAsync((char*)Xout + (size_t)xmap[s] * bytes,
+                                (char*)w.X + (size_t)s * bytes, bytes, hipMemcpyDeviceToDevice,
+                                c->stream));
+  }
+  cr.iters = hf.iter;
+  // A breakdown or non-finite value inside the iteration stops it with the
+  // last finite iterate in X (the update of that step is skipped); the true
+  // residual check and defect correction then decide. Only a failure of the
+  // initial QR (linearly dependent columns of B) is final.
+  if (hf.error && hf.iter == 0) cr.error = hf.error;
+  else if (hf.error) cr.soft = hf.error;
+  return BMS_OK;
+}
 
 }  // namespace
 
-// true relative residuals |b_i - (A + s)x_i| / |b_i| of user-ordered solutions
-int true_residuals(bms_ctx* c, double mass, int n, int ns, const double* shifts, const void* B,
-                   const void* X, double* res_host) {
+// Per shift s and column i of user-ordered solutions: rn2[s][i] = |b_i - (A+s)x_i|^2
+// and bn2[i] = |b_i|^2.
+static int residual_norms(bms_ctx* c, double mass, int n, int ns, const double* shifts,
+                          const void* B, const void* X, std::vector<double>& rn2,
+                          std::vector<double>& bn2) {
   int rc;
   int rows = 3 * c->vh;
   size_t blk = (size_t)rows * n;
   void *t1, *t2, *out;
-  if ((rc = scratch_buf(c, S_W1, blk * sizeof(double2), &t1))) return rc;
-  if ((rc = scratch_buf(c, S_W, blk * sizeof(double2), &t2))) return rc;
+  if ((rc = scratch_buf(c, S_R1, blk * sizeof(double2), &t1))) return rc;
+  if ((rc = scratch_buf(c, S_R2, blk * sizeof(double2), &t2))) return rc;
   if ((rc = scratch_buf(c, S_RES, (size_t)ns * n * sizeof(double2) + 64, &out))) return rc;
   int nb = gram_blocks(rows, n);
   void* pp;
-  if ((rc = scratch_buf(c, S_PART, (size_t)nb * n * n * sizeof(double2) + 64, &pp))) return rc;
+  if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
   void* fp;
-  if ((rc = scratch_buf(c, S_FLAGS, sizeof(SolverFlags) + 64, &fp))) return rc;
-  int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2;
+  if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
+  int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2 * CNT_STRIDE;
   for (int s = 0; s < ns; ++s) {
     const double2* xs = (const double2*)X + s * blk;
     HIP_TRY(c, launch_hop<double>(c, 1, n, xs, t1, nullptr, 0.0, 1.0, nullptr));
@@ -213,8 +368,10 @@ int true_residuals(bms_ctx* c, double mass, int n, int ns, const double* shifts,
   HIP_TRY(c, hipMemcpyAsync(h.data(), out, h.size() * sizeof(double2), hipMemcpyDeviceToHost,
                             c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (size_t i = 0; i < h.size(); ++i)
-    res_host[i] = h[i].y > 0 ? std::sqrt(h[i].x / h[i].y) : std::sqrt(h[i].x);
+  rn2.resize((size_t)ns * n);
+  bn2.resize(n);
+  for (size_t i = 0; i < h.size(); ++i) rn2[i] = h[i].x;
+  for (int i = 0; i < n; ++i) bn2[i] = h[i].y;
   return BMS_OK;
 }
 
@@ -230,7 +387,8 @@ static int validate_solve(bms_ctx* c, double mass, int n, int ns, const double* 
       return set_err(c, BMS_EINVAL, "shift %d is negative or not finite", s);
   if (!std::isfinite(mass)) return set_err(c, BMS_EINVAL, "mass not finite");
   if (!(tol > 0) || !(tol < 1)) return set_err(c, BMS_EINVAL, "tol must be in (0, 1)");
-  if (max_iter < 1) return set_err(c, BMS_EINVAL, "max_iter must be >= 1");
+  if (max_iter < 1 || max_iter > 10000000)
+    return set_err(c, BMS_EINVAL, "max_iter must be in [1, 1e7]");
   if (!B || !X) return set_err(c, BMS_EINVAL, "null B or X");
   if (B == X) return set_err(c, BMS_EINVAL, "B and X must not alias");
   if (o) {
@@ -249,94 +407,126 @@ static int validate_solve(bms_ctx* c, double mass, int n, int ns, const double* 
 }
 
 template <typename T>
-static int solve_f64(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
-                     int max_iter, const bms_opts& o, const void* B, void* X, bms_stats* st) {
+static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double* shifts,
+                           double tol, int max_iter, const bms_opts& o, const void* B, void* X,
+                           bms_stats* st) {
   int rc;
   std::vector<int> order(ns);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shifts[a] < shifts[b]; });
-  SmallParams sp;
-  memset(&sp, 0, sizeof sp);
-  sp.n = n;
-  sp.ns = ns;
-  sp.max_iter = max_iter;
-  sp.tol = tol;
-  double ft = o.freeze_tol > 0 ? o.freeze_tol : tol;
-  sp.freeze_tol = ft < tol ? ft : tol;
-  // a computed Gram resolves pivots only down to ~eps * trace
-  sp.breakdown_tol = 10.0 * n * 2.220446049250313e-16;
-  for (int s = 0; s < ns; ++s) sp.sigma[s] = shifts[order[s]];
-  Work w;
-  if ((rc = alloc_work<T>(c, n, ns, max_iter, w))) return rc;
-  if ((rc = enqueue_setup<T>(c, w, sp, B))) return rc;
-  SolverFlags hf;
-  int K = o.check_interval;
-  long enqueued = 0;
-  if (c->timing && (int)c->evpool.size() < 8 * K) {
-    size_t old = c->evpool.size();
-    c->evpool.resize(8 * K);
-    for (size_t i = old; i < c->evpool.size(); ++i) HIP_TRY(c, hipEventCreate(&c->evpool[i]));
-  }
-  std::vector<float> upd_ms;  // per completed iteration, update kernel time
-  while (true) {
-    for (int k = 0; k < K; ++k)
-      if ((rc = enqueue_iteration<T>(c, w, sp, mass, c->timing ? &c->evpool[8 * k] : nullptr)))
-        return rc;
-    HIP_TRY(c, hipMemcpyAsync(&hf, w.flags, sizeof hf, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->timing) {
-      double G = 72.0 * c->vol * sizeof(T);
-      double S = (double)w.blk * sizeof(cplx<T>);
-      const double kbytes[7] = {G + 2 * S, G + 3 * S, 2 * S, 0, 2 * S, 0, 0};
-      for (int k = 0; k < K; ++k) {
-        if (enqueued + k >= hf.iter) break;  // launches after the stop did no work
-        for (int i = 0; i < 7; ++i) {
-          float ms = 0;
-          HIP_TRY(c, hipEventElapsedTime(&ms, c->evpool[8 * k + i], c->evpool[8 * k + i + 1]));
-          int kc = kIterKernel[i];
-          c->kt_ms[kc] += ms;
-          c->kt_launches[kc] += 1;
-          c->kt_bytes[kc] += kbytes[i];
-          if (i == 6) upd_ms.push_back(ms);
-        }
-      }
+  std::vector<double> sig(ns);
+  for (int s = 0; s < ns; ++s) sig[s] = shifts[order[s]];
+  CoreResult cr;
+  if ((rc = solve_core<T>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X, cr)))
+    return rc;
+  int refine_iters = 0, reliable = cr.reliable;
+  std::vector<double> rn2, bn2;
+  if ((rc = residual_norms(c, mass, n, ns, shifts, B, X, rn2, bn2))) return rc;
+  // defect correction of the shifts that miss tol
+  int rows = 3 * c->vh;
+  size_t blk = (size_t)rows * n;
+  for (int round = 0; round < o.max_refine && !cr.error; ++round) {
+    std::vector<int> bad;
+    for (int s = 0; s < ns; ++s) {
+      double m = 0;
+      for (int i = 0; i < n; ++i) m = std::max(m, std::sqrt(rn2[s * n + i] / bn2[i]));
+      if (!(m <= tol)) bad.push_back(s);
     }
-    enqueued += K;
-    if (hf.stop) break;
-    if (enqueued > (long)max_iter + 2L * K)  // the device stops itself at max_iter
-      return set_err(c, BMS_EHIP, "device iteration control did not stop (iter %d)", hf.iter);
+    if (bad.empty()) break;
+    void *RB, *E, *cols, *t1, *t2;
+    if ((rc = scratch_buf(c, S_RB, blk * sizeof(double2), &RB))) return rc;
+    if ((rc = scratch_buf(c, S_E, blk * sizeof(double2), &E))) return rc;
+    if ((rc = scratch_buf(c, S_COLS, 3 * n * sizeof(double) + 64, &cols))) return rc;
+    if ((rc = scratch_buf(c, S_R1, blk * sizeof(double2), &t1))) return rc;
+    if ((rc = scratch_buf(c, S_R2, blk * sizeof(double2), &t2))) return rc;
+    for (int s : bad) {
+      // column-normalised residual R'_i = r_i / |r_i| (B's column if r_i = 0)
+      std::vector<double> h(3 * n);
+      double worst = 0;
+      for (int i = 0; i < n; ++i) {
+        double rn = std::sqrt(rn2[s * n + i]), bn = std::sqrt(bn2[i]);
+        h[i] = rn > 0 ? 1.0 / rn : 0.0;
+        h[n + i] = bn > 0 ? 1.0 / bn : 1.0;
+        h[2 * n + i] = rn;
+        worst = std::max(worst, rn / bn);
+      }
+      if (!std::isfinite(worst)) {
+        cr.error = BMS_ENAN;
+        break;
+      }
+      const double2* xs = (const double2*)X + s * blk;
+      HIP_TRY(c, hipMemcpyAsync(cols, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream));
+      HIP_TRY(c, launch_hop<double>(c, 1, n, xs, t1, nullptr, 0.0, 1.0, nullptr));
+      HIP_TRY(c, launch_hop<double>(c, 0, n, t1, t2, xs, mass * mass + shifts[s], -1.0, nullptr));
+      HIP_TRY(c, launch_resid_block(c->stream, rows, n, B, t2, (const double*)cols,
+                                    (const double*)cols + n, RB, nullptr));
+      double tin = 0.5 * tol / worst;
+      tin = std::min(0.5, std::max(tin, 1e-13));
+      CoreResult ci;
+      int zero = 0;
+      double sg = shifts[s];
+      if ((rc = solve_core<T>(c, mass, n, 1, &sg, &zero, tin, max_iter, o, RB, E, ci))) return rc;
+      refine_iters += ci.iters;
+      reliable += ci.reliable;
+      if (ci.error == BMS_EBREAKDOWN) {
+        // the normalised residual columns are nearly dependent (typically a
+        // few lowest modes left): refine them one column at a time
+        void *bc, *ec;
+        if ((rc = scratch_buf(c, S_RBC, (size_t)rows * sizeof(double2), &bc))) return rc;
+        if ((rc = scratch_buf(c, S_EC, (size_t)rows * sizeof(double2), &ec))) return rc;
+        for (int i = 0; i < n; ++i) {
+          if (!(h[2 * n + i] > 0.5 * tol * std::sqrt(bn2[i]))) continue;
+          double ti = std::min(0.5, std::max(0.5 * tol * std::sqrt(bn2[i]) / h[2 * n + i], 1e-13));
+          HIP_TRY(c, launch_gather_col(c->stream, rows, n, i, RB, bc));
+          CoreResult cc;
+          if ((rc = solve_core<T>(c, mass, 1, 1, &sg, &zero, ti, max_iter, o, bc, ec, cc)))
+            return rc;
+          refine_iters += cc.iters;
+          reliable += cc.reliable;
+          if (cc.error) {
+            cr.error = cc.error;
+            break;
+          }
+          HIP_TRY(c, launch_scatter_axpy_col(c->stream, rows, n, i, (double2*)X + s * blk, ec,
+                                             h[2 * n + i]));
+        }
+        if (cr.error) break;
+        continue;
+      }
+      if (ci.error) {
+        cr.error = ci.error;
+        break;
+      }
+      HIP_TRY(c, launch_axpy_cols(c->stream, rows, n, (double2*)X + s * blk, E,
+                                  (const double*)cols + 2 * n));
+    }
+    if ((rc = residual_norms(c, mass, n, ns, shifts, B, X, rn2, bn2))) return rc;
   }
-  if (c->timing && hf.iter > 0) {
-    std::vector<int> nact(hf.iter);
-    HIP_TRY(c, hipMemcpyAsync(nact.data(), w.sm.nact_log, hf.iter * sizeof(int),
-                              hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    double S = (double)w.blk * sizeof(cplx<T>);
-    for (int k = 0; k < hf.iter; ++k) c->kt_bytes[BMS_KERNEL_UPDATE] += (3.0 + 4.0 * nact[k]) * S;
-  }
-  // solutions back to the caller's shift order
-  size_t bytes = w.blk * sizeof(double2);
-  for (int s = 0; s < ns; ++s)
-    HIP_TRY(c, hipMemcpyAsync((char*)X + (size_t)order[s] * bytes, (char*)w.X + (size_t)s * bytes,
-                              bytes, hipMemcpyDeviceToDevice, c->stream));
-  std::vector<double> res((size_t)ns * n);
-  if ((rc = true_residuals(c, mass, n, ns, shifts, B, X, res.data()))) return rc;
   double mx = 0;
-  for (double r : res) mx = std::max(mx, std::isfinite(r) ? r : 1e300);
+  std::vector<double> res((size_t)ns * n);
+  for (int s = 0; s < ns; ++s)
+    for (int i = 0; i < n; ++i) {
+      double r = bn2[i] > 0 ? std::sqrt(rn2[s * n + i] / bn2[i]) : std::sqrt(rn2[s * n + i]);
+      res[s * n + i] = r;
+      mx = std::max(mx, std::isfinite(r) ? r : 1e300);
+    }
   if (st) {
-    st->iterations = hf.iter;
-    st->hop_calls = 2 * hf.iter + 2 * ns;
-    st->reliable_updates = 0;
-    st->refine_iterations = 0;
+    st->iterations = cr.iters;
+    st->hop_calls = 2 * (cr.iters + refine_iters) + 2 * ns;
+    st->reliable_updates = reliable;
+    st->refine_iterations = refine_iters;
     st->converged = mx <= tol;
     st->max_true_residual = mx;
     if (st->true_residual) memcpy(st->true_residual, res.data(), res.size() * sizeof(double));
   }
-  if (hf.error) return set_err(c, hf.error, "device reported %s after %d iterations",
-                               bms_error_string(hf.error), hf.iter);
+  if (cr.error)
+    return set_err(c, cr.error, "device reported %s in the initial QR", bms_error_string(cr.error));
+  if (!(mx < 1e300))
+    return set_err(c, BMS_ENAN, "non-finite true residual after %d iterations", cr.iters);
   if (mx > tol)
     return set_err(c, BMS_ENOCONV, "max true residual %.3e > tol %.3e after %d iterations", mx,
-                   tol, hf.iter);
+                   tol, cr.iters);
   return BMS_OK;
 }
 
@@ -351,9 +541,9 @@ extern "C" int bms_solve(bms_ctx* c, double mass, int n, int ns, const double* s
   if (opts) o = *opts;
   if ((rc = stream_begin(c))) return rc;
   if (o.precision == BMS_PREC_F64)
-    rc = solve_f64<double>(c, mass, n, ns, shifts, tol, max_iter, o, B, X, st);
+    rc = solve_precision<double>(c, mass, n, ns, shifts, tol, max_iter, o, B, X, st);
   else
-    rc = set_err(c, BMS_EINVAL, "BMS_PREC_MIXED not available yet");
+    rc = solve_precision<float>(c, mass, n, ns, shifts, tol, max_iter, o, B, X, st);
   int rc2 = stream_end(c);
   return rc ? rc : rc2;
 }
@@ -364,6 +554,7 @@ extern "C" int bms_action(bms_ctx* c, int n, int ns, double a0, const double* al
   if (n < 1 || n > BMS_MAX_RHS) return set_err(c, BMS_EINVAL, "n must be in [1, %d]", BMS_MAX_RHS);
   if (ns < 0 || ns > BMS_MAX_SHIFTS) return set_err(c, BMS_EINVAL, "bad n_shifts");
   if ((ns > 0 && (!alpha || !X)) || !B || !S) return set_err(c, BMS_EINVAL, "null pointer");
+  if (!c->gauge_set) return set_err(c, BMS_ESTATE, "no gauge field set");
   int rc;
   if ((rc = stream_begin(c))) return rc;
   int rows = 3 * c->vh;
@@ -372,9 +563,9 @@ extern "C" int bms_action(bms_ctx* c, int n, int ns, double a0, const double* al
     return rc;
   al = (double2*)out + n;
   int nb = gram_blocks(rows, n);
-  if ((rc = scratch_buf(c, S_PART, (size_t)nb * n * n * sizeof(double2) + 64, &pp))) return rc;
-  if ((rc = scratch_buf(c, S_FLAGS, sizeof(SolverFlags) + 64, &fp))) return rc;
-  int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2;
+  if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
+  if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
+  int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2 * CNT_STRIDE;
   if (ns > 0)
     HIP_TRY(c, hipMemcpyAsync(al, alpha, ns * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_action(c->stream, rows, n, ns, a0, (const double*)al, B, X, (double2*)out,

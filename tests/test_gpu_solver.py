@@ -5,7 +5,8 @@ P1 (hard): every column of every shift has true FP64 relative residual
 P2:        X^(s) within rtol of the oracle's multi-shift CG solution at 1e-13;
            the GPU runs at tol 1e-12 so that the difference is set by the
            conditioning bound kappa_s * 1e-12 (kappa_s <= (16+m^2+s)/(m^2+s)).
-P3:        FP64 iteration count within +-2 of the oracle's Algorithm 1.
+P3:        FP64 iteration count within +-2 of the oracle's Algorithm 1 (both
+           stopping when every residual estimate is below tol/2).
 """
 import numpy as np
 import pytest
@@ -61,8 +62,8 @@ def test_solver_parity_f64(torch, name):
     for s in range(len(r.beta)):
         bound = max(1e-9, 5 * _kappa(m, r.beta[s]) * 1e-12)
         assert np.linalg.norm(X[s] - Xo[s]) <= bound * np.linalg.norm(Xo[s])
-    # P3
-    oo = O.sbcgrq_lattice(dims, BC, U, m, r.beta, B, 1e-12)
+    # P3: the solver stops when every estimate is below tol/2
+    oo = O.sbcgrq_lattice(dims, BC, U, m, r.beta, B, 0.5e-12)
     assert abs(st["iterations"] - oo["iters"]) <= 2
 
 
