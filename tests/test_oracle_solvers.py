@@ -133,3 +133,32 @@ def test_free_field_block_solve(bc):
     for s, sig in enumerate(sh):
         xf = F.solve(dims, bc, 0.1, sig, B)
         assert np.abs(o["X"][s] - xf).max() < 1e-9 * np.abs(xf).max()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_action_equals_spectral_rational(name):
+    """S_i = phi_i^dag r(A) phi_i (eq. RA in the action of Sec. II) from the
+    eigendecomposition of the dense A on 2^4, and r(A) phi close to A^-p phi
+    within the fit's relative error: pins action() and the coefficients
+    without the oracle's own solvers."""
+    dims = (2, 2, 2, 2)
+    w = configs.WORKLOADS[name]
+    r = configs.workload_coefficients(name)
+    m = w["mass"]
+    U = random_gauge(dims, w["eps"], 77)
+    B = gaussian_block(dims, 3, 78)
+    A = O.dense_operator(dims, BC, U, m, 0.0)
+    lam, V = np.linalg.eigh(A)
+    assert lam.min() > m * m * (1 - 1e-12) and lam.max() < 16 + m * m
+    rl = r.a0 + sum(a / (lam + b) for a, b in zip(r.alpha, r.beta))
+    Bf = B.reshape(-1, B.shape[-1])
+    C = np.conj(V).T @ Bf
+    S_spec = np.real(np.sum(np.conj(C) * (rl[:, None] * C), axis=0))
+    X, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-14)
+    S = O.action(B, X, r.a0, r.alpha)
+    assert np.allclose(S, S_spec, rtol=1e-11, atol=0)
+    # the rational function approximates x^-p to its stated relative error
+    exact = lam ** (-w["power"])
+    assert np.max(np.abs(rl / exact - 1)) <= 1.01 * r.error
+    S_exact = np.real(np.sum(np.conj(C) * (exact[:, None] * C), axis=0))
+    assert np.all(np.abs(S / S_exact - 1) <= 1.01 * r.error)
