@@ -81,7 +81,8 @@ typedef struct bms_opts {
   int check_interval;     /* iterations between host-side convergence checks (8) */
   int max_refine;         /* MIXED: rounds of per-shift defect correction (4) */
   int qr_passes;          /* Cholesky-QR passes per iteration, 1 or 2 (1) */
-  int use_graph;          /* replay iteration chunks as a captured hipGraph (1) */
+  int use_graph;          /* reserved: accepted and ignored (iteration chunks are
+                             launched directly on the stream) */
 } bms_opts;
 
 /* Solver statistics (filled on BMS_OK, BMS_ENOCONV and BMS_EBREAKDOWN). */
@@ -107,8 +108,8 @@ const char* bms_last_error(const bms_ctx* ctx);
  * Create a context for one lattice. dims and bc as above; stream is a
  * hipStream_t (NULL = the default stream). Performs no device work; device
  * memory is allocated by bms_set_gauge and the first call of each shape.
- * Errors: BMS_EINVAL for a null ctx, odd or < 2 extents, bc not +-1, or a
- * volume above 2^28 sites.
+ * Errors: BMS_EINVAL for a null ctx, odd or < 2 extents, an extent above 4096,
+ * bc not +-1, or a volume above 2^25 sites.
  */
 int bms_create(bms_ctx** ctx, const int dims[4], const int bc[4], void* stream);
 
@@ -198,7 +199,7 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
  *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per active
  *                       shift P^(s), X^(s) read and written
  *   BMS_KERNEL_SMALL    the n x n kernels (no block data)
- * Timing disables graph replay. bms_timing_enable(ctx, 1) also clears the
+ * bms_timing_enable(ctx, 1) also clears the
  * accumulators; bms_timing_read returns them (host pointers, any may be NULL).
  */
 #define BMS_KERNEL_HOP 0
@@ -211,12 +212,14 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
 int bms_timing_enable(bms_ctx* ctx, int enable);
 
 /*
- * Kernel variant selection (what bms_autotune chooses). For BMS_KERNEL_UPDATE
- * at n = 8 or 16: 0 = four row chunks per work-group with both coefficient
+ * Kernel variant selection. For BMS_KERNEL_UPDATE: 4 = the matrix-core
+ * (MFMA) kernel, used for FP64 at n = 8 and 16; 0..3 = the vector kernels
+ * at n = 8 and 16 (0 = four row chunks per work-group with both coefficient
  * columns in registers, 1 = two chunks, one column at a time, 2 = four
- * chunks, one column at a time (the built-in default), 3 = two chunks, both
- * columns; -1 restores the built-in default. Other widths and kernels ignore the setting. Results do
- * not depend on the variant beyond rounding order.
+ * chunks, one column at a time, 3 = two chunks, both columns); -1 restores
+ * the built-in default (4 where it applies, else 2). Other widths and
+ * precisions ignore the setting. Results do not depend on the variant beyond
+ * rounding order.
  */
 int bms_set_variant(bms_ctx* ctx, int kernel, int variant);
 int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,

@@ -234,7 +234,7 @@ extern "C" int bms_timing_read(const bms_ctx* c, int kernel, double* ms, long lo
 extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
   if (!c) return BMS_EINVAL;
   if (kernel != BMS_KERNEL_UPDATE) return set_err(c, BMS_EINVAL, "no variants for kernel %d", kernel);
-  if (variant < -1 || variant > 3) return set_err(c, BMS_EINVAL, "variant must be in [-1, 3]");
+  if (variant < -1 || variant > 4) return set_err(c, BMS_EINVAL, "variant must be in [-1, 4]");
   c->update_variant = variant;
   return BMS_OK;
 }

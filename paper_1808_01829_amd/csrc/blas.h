@@ -34,6 +34,9 @@ hipError_t launch_update(hipStream_t st, const UpdateArgs<T, TX>& a);
 // variant 0: both coefficient columns in registers; 1: one at a time
 template <typename T, typename TX>
 hipError_t launch_update_fast(hipStream_t st, const UpdateArgs<T, TX>& a, int variant);
+// FP64 update on the matrix cores (update_mfma.hip), for n = 8 and 16
+bool update_mfma_supported(int n);
+hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<double, double>& a);
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
                               double2* out, double2* partials, int* counter, int nb);
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,

@@ -42,7 +42,7 @@ struct bms_ctx {
   DevBuf links64, links32;  // [parity][blocked links] complex
   std::vector<DevBuf> scratch;  // named by slot index
   std::string last_error;
-  // kernel variants (bms_autotune); -1 = built-in default
+  // kernel variants (bms_set_variant); -1 = built-in default
   int update_variant = -1;
   // per-kernel timing (bms_timing_enable)
   bool timing = false;

@@ -25,6 +25,8 @@
 #include <numeric>
 #include <vector>
 
+#include <type_traits>
+
 #include "blas.h"
 
 namespace {
@@ -180,8 +182,17 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   ua.Mp = (const cplx<T>*)w.Mp;
   ua.flags = w.flags;
   for (int s = 0; s < BMS_MAX_SHIFTS; ++s) ua.xidx[s] = s < w.ns ? s : 0;
-  // built-in default: four row chunks, one coefficient column at a time
-  HIP_TRY(c, (launch_update_fast<T, T>(c->stream, ua, c->update_variant < 0 ? 2 : c->update_variant)));
+  // built-in default: the matrix-core kernel in FP64 where it exists, else
+  // four row chunks with one coefficient column at a time
+  const int uv = c->update_variant;
+  bool on_mfma = false;
+  if constexpr (std::is_same<T, double>::value) {
+    if (update_mfma_supported(w.n) && (uv < 0 || uv == 4)) {
+      HIP_TRY(c, launch_update_mfma(c->stream, ua));
+      on_mfma = true;
+    }
+  }
+  if (!on_mfma) HIP_TRY(c, (launch_update_fast<T, T>(c->stream, ua, uv < 0 || uv == 4 ? 2 : uv)));
   MARK(7);
 #undef MARK
   return BMS_OK;
