@@ -217,9 +217,13 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  * at n = 8 and 16 (0 = four row chunks per work-group with both coefficient
  * columns in registers, 1 = two chunks, one column at a time, 2 = four
  * chunks, one column at a time, 3 = two chunks, both columns); -1 restores
- * the built-in default (4 where it applies, else 2). Other widths and
- * precisions ignore the setting. Results do not depend on the variant beyond
- * rounding order.
+ * the built-in default (4 where it applies, else 2). For BMS_KERNEL_GRAM:
+ * 1 and 2 = the matrix-core kernel (n = 8 and 16, FP32 or FP64 inputs, FP64
+ * accumulation) with 4 or 8 row steps in flight per wave, 0 = the vector
+ * kernel, -1 = the default (2 where it applies).
+ * Other kernels are rejected with BMS_EINVAL; other widths and precisions
+ * ignore the setting. Results do not depend on the variant beyond rounding
+ * order.
  */
 int bms_set_variant(bms_ctx* ctx, int kernel, int variant);
 int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,

@@ -85,6 +85,7 @@ extern "C" int bms_create(bms_ctx** out, const int dims[4], const int bc[4], voi
 int ensure_device(bms_ctx* c) {
   if (c->stream) return BMS_OK;
   HIP_TRY(c, hipGetDevice(&c->device));
+  HIP_TRY(c, hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   HIP_TRY(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -233,8 +234,13 @@ extern "C" int bms_timing_read(const bms_ctx* c, int kernel, double* ms, long lo
 
 extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
   if (!c) return BMS_EINVAL;
+  if (kernel == BMS_KERNEL_GRAM) {
+    if (variant < -1 || variant > 3) return set_err(c, BMS_EINVAL, "gram variant must be in [-1, 3]");
+    c->gram_variant = variant;
+    return BMS_OK;
+  }
   if (kernel != BMS_KERNEL_UPDATE) return set_err(c, BMS_EINVAL, "no variants for kernel %d", kernel);
-  if (variant < -1 || variant > 4) return set_err(c, BMS_EINVAL, "variant must be in [-1, 4]");
+  if (variant < -1 || variant > 5) return set_err(c, BMS_EINVAL, "variant must be in [-1, 5]");
   c->update_variant = variant;
   return BMS_OK;
 }

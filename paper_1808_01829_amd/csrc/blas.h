@@ -34,9 +34,11 @@ hipError_t launch_update(hipStream_t st, const UpdateArgs<T, TX>& a);
 // variant 0: both coefficient columns in registers; 1: one at a time
 template <typename T, typename TX>
 hipError_t launch_update_fast(hipStream_t st, const UpdateArgs<T, TX>& a, int variant);
-// FP64 update on the matrix cores (update_mfma.hip), for n = 8 and 16
+// update on the matrix cores (update_mfma.hip), for n = 8 and 16, with one or
+// two 16-row tiles per wave; F = double or float (the Q step is FP64 in both)
 bool update_mfma_supported(int n);
-hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<double, double>& a);
+template <typename F>
+hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<F, F>& a, bool two_tiles);
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
                               double2* out, double2* partials, int* counter, int nb);
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,
@@ -97,7 +99,9 @@ hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s,
 template <typename T>
 hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
                                      SolverFlags* fl, cplx<T>* Mp);
+// variant 0: vector kernel; otherwise the matrix-core kernel where it exists (n = 8, 16)
 template <typename T>
 hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const void* Q,
                         const void* W, double2* G4, double2* partials, int* counter, int nb,
-                        const int* skip);
+                        const int* skip, int variant = -1);
+bool gram4_mfma_supported(int n);

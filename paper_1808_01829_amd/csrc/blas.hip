@@ -364,12 +364,16 @@ __global__ __launch_bounds__(BMS_WG) void k_action(int rows, int n, int per_bloc
 
 }  // namespace
 
-int gram_blocks(int rows, int n) {
-  // enough blocks to fill the chip, each with at least a few chunks of rows
+int gram_blocks(int rows, int n, int num_cu) {
+  // enough blocks to fill the chip, each with at least a few chunks of rows;
+  // on a large block the count is a whole number of rounds of three
+  // resident blocks per compute unit (no partly filled last round)
   int C = BMS_WG / n;
   int per = 4 * C;
   int nb = (rows + per - 1) / per;
-  return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+  int cap = num_cu > 0 ? 3 * num_cu : MAX_RED_BLOCKS;
+  if (cap > MAX_RED_BLOCKS) cap = MAX_RED_BLOCKS;
+  return nb < 1 ? 1 : (nb > cap ? cap : nb);
 }
 
 static int rows_per_block(int rows, int nb) { return (rows + nb - 1) / nb; }
@@ -614,6 +618,297 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4(int rows, int n, int per_block
   last_block_sum(partials, G4, 4 * nn, counter);
 }
 
+// ---- the four Grams of one iteration on the matrix cores --------------------
+// Real Gram tiles R = sum_rows x^T y (v_mfma_f64_16x16x4, 4 rows per step;
+// the lane holding row l/16, column l%16 of a 16-column tile serves as either
+// operand), FP64 accumulation for FP32 and FP64 inputs.
+//  n = 16: tile 0 holds the real parts of the 16 complex columns and tile 1 the
+//          imaginary parts, so each lane loads one whole complex per block and
+//          step; G[i][j] = R00[i][j] + R11[i][j] + i (R01[i][j] - R10[i][j]).
+//  n = 8:  one tile of the 16 interleaved reals; G[i][j] = R[2i][2j] +
+//          R[2i+1][2j+1] + i (R[2i][2j+1] - R[2i+1][2j]).
+// W^H W and Q^H Q are symmetric in real form: only tiles a <= b are summed.
+// D steps of 4 rows are in flight per wave (a register ring).
+typedef double gdx4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int N>
+struct GramRow {
+  static constexpr int NT = 2 * N / 16;
+  // the NT operand values of this lane for row r of block X; rows outside the
+  // range read row 0 and contribute zero (no branch around the load, so the
+  // loads of the ring stay in flight together)
+  __device__ static __forceinline__ void load(const cplx<T>* X, int r, bool ok, int c,
+                                              double (&v)[NT]) {
+    const size_t rc = ok ? (size_t)r : 0;
+    if constexpr (N == 16) {
+      cplx<T> z = X[rc * N + c];
+      v[0] = ok ? (double)z.x : 0.0;
+      v[1] = ok ? (double)z.y : 0.0;
+    } else {
+      const T* x = (const T*)X;
+      T z = x[rc * 2 * N + c];
+      v[0] = ok ? (double)z : 0.0;
+    }
+  }
+  // complex Gram entry (i, j) from the real Gram R (NR x NR, tile-major)
+  __device__ static __forceinline__ double2 entry(const double* R, int i, int j) {
+    constexpr int NR = 2 * N;
+    if constexpr (N == 16)
+      return make_double2(R[i * NR + j] + R[(16 + i) * NR + 16 + j],
+                          R[i * NR + 16 + j] - R[(16 + i) * NR + j]);
+    else
+      return make_double2(R[(2 * i) * NR + 2 * j] + R[(2 * i + 1) * NR + 2 * j + 1],
+                          R[(2 * i) * NR + 2 * j + 1] - R[(2 * i + 1) * NR + 2 * j]);
+  }
+};
+
+template <typename T, int N, int D>
+__global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
+                                                       const cplx<T>* __restrict__ P,
+                                                       const cplx<T>* __restrict__ Q,
+                                                       const cplx<T>* __restrict__ W,
+                                                       double2* __restrict__ G4,
+                                                       double2* __restrict__ partials,
+                                                       int* __restrict__ counter,
+                                                       const int* __restrict__ skip) {
+  using GR = GramRow<T, N>;
+  constexpr int NR = 2 * N, NT = GR::NT, NN = N * N;
+  constexpr int NPAIR = NT * (NT + 1) / 2;  // tiles a <= b of a symmetric product
+  __shared__ double red[4][NR * NR];        // one real Gram per wave
+  if (skip && *skip) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const RowRange rr = block_rows(rows, per_block);
+  gdx4 apw[NT][NT], aqw[NT][NT], aww[NPAIR], aqq[NPAIR];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) apw[a][b] = aqw[a][b] = gdx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < NPAIR; ++e) aww[e] = aqq[e] = gdx4{0.0, 0.0, 0.0, 0.0};
+  // steps of 4 rows, dealt round-robin to the waves; a ring of D steps in flight
+  const int nsteps = (rr.r1 - rr.r0 + 3) >> 2;
+  double p[D][NT], q[D][NT], w[D][NT];
+  auto load = [&](int st, double (&pv)[NT], double (&qv)[NT], double (&wv)[NT]) {
+    int r = rr.r0 + 4 * st + g;
+    bool ok = st < nsteps && r < rr.r1;
+    GR::load(P, r, ok, c, pv);
+    GR::load(Q, r, ok, c, qv);
+    GR::load(W, r, ok, c, wv);
+  };
+#pragma unroll
+  for (int u = 0; u < D; ++u) load(wave + 4 * u, p[u], q[u], w[u]);
+  for (int st = wave; st < nsteps; st += 4 * D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      double pc[NT], qc[NT], wc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        pc[t] = p[u][t];
+        qc[t] = q[u][t];
+        wc[t] = w[u][t];
+      }
+      load(st + 4 * (u + D), p[u], q[u], w[u]);
+#pragma unroll
+      for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+          apw[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pc[a], wc[b], apw[a][b], 0, 0, 0);
+          aqw[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(qc[a], wc[b], aqw[a][b], 0, 0, 0);
+        }
+      int e = 0;
+#pragma unroll
+      for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = a; b < NT; ++b, ++e) {
+          aww[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[a], wc[b], aww[e], 0, 0, 0);
+          aqq[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(qc[a], qc[b], aqq[e], 0, 0, 0);
+        }
+    }
+  }
+  // one product at a time: every wave writes its real Gram (accumulator
+  // element k of lane (g, c) is tile row g + 4k, column c), then the block
+  // sums the four and forms the complex entries of its partial
+  double* R = red[wave];
+  auto put = [&](int a, int b, const gdx4& d, bool mirror) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int i = a * 16 + g + 4 * k, j = b * 16 + c;
+      R[i * NR + j] = d[k];
+      if (mirror) R[j * NR + i] = d[k];
+    }
+  };
+  double2* part = partials + (size_t)blockIdx.x * 4 * NN;
+  auto reduce = [&](int gi) {
+    __syncthreads();
+    for (int e = tid; e < NN; e += BMS_WG) {
+      int i = e / N, j = e - (e / N) * N;
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) s = cadd(s, GR::entry(red[v], i, j));
+      part[gi * NN + e] = s;
+    }
+    __syncthreads();
+  };
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) put(a, b, apw[a][b], false);
+  reduce(0);
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) put(a, b, aqw[a][b], false);
+  reduce(1);
+  {
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = a; b < NT; ++b, ++e) put(a, b, aww[e], a != b);
+  }
+  reduce(2);
+  {
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = a; b < NT; ++b, ++e) put(a, b, aqq[e], a != b);
+  }
+  reduce(3);
+  last_block_sum(partials, G4, 4 * NN, counter);
+}
+
+// Same four Grams, the rows shared through LDS: the block stages chunks of
+// GCH rows of P, Q and W (coalesced, the next chunk prefetched into registers
+// while the current one is reduced) and each wave owns one product:
+// wave 0 P^H W, 1 Q^H W, 2 W^H W, 3 Q^H Q, so a wave holds at most four tiles.
+constexpr int GCH = 32;
+
+template <typename T, int N>
+__global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
+                                                      const cplx<T>* __restrict__ P,
+                                                      const cplx<T>* __restrict__ Q,
+                                                      const cplx<T>* __restrict__ W,
+                                                      double2* __restrict__ G4,
+                                                      double2* __restrict__ partials,
+                                                      int* __restrict__ counter,
+                                                      const int* __restrict__ skip) {
+  using C_ = cplx<T>;
+  using GR = GramRow<T, N>;
+  constexpr int NR = 2 * N, NT = GR::NT, NN = N * N;
+  constexpr int RS = N + 1;            // staged row stride (complex), padded
+  constexpr int BS = GCH * RS;         // one staged block
+  constexpr int PER_T = GCH * N / BMS_WG;  // complex per thread and block
+  static_assert(PER_T >= 1 && GCH * N % BMS_WG == 0, "chunk must cover the block");
+  constexpr int STAGE = 2 * 3 * BS * (int)sizeof(C_);
+  constexpr int REDB = 4 * NR * NR * (int)sizeof(double);
+  __shared__ __align__(16) unsigned char smem[STAGE > REDB ? STAGE : REDB];
+  if (skip && *skip) return;
+  C_* stage = (C_*)smem;  // [2][3][GCH][RS]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const RowRange rr = block_rows(rows, per_block);
+  const C_* src[3] = {P, Q, W};
+  // this wave's product: x block and y block (0 = P, 1 = Q, 2 = W)
+  const int xb = wave == 0 ? 0 : (wave == 2 ? 2 : 1);
+  const int yb = wave == 3 ? 1 : 2;
+  const bool sym = wave >= 2;
+  gdx4 acc[NT][NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = gdx4{0.0, 0.0, 0.0, 0.0};
+  // chunk loader: element e = tid + k*256 of the chunk's rows x N complex
+  C_ nx[3][PER_T];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int k = 0; k < PER_T; ++k) {
+        int e = tid + k * BMS_WG;
+        int r = r0 + e / N;
+        bool ok = r < rr.r1;
+        C_ z = src[b][(size_t)(ok ? r : 0) * N + (e % N)];
+        nx[b][k] = ok ? z : czero<C_>();
+      }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int k = 0; k < PER_T; ++k) {
+        int e = tid + k * BMS_WG;
+        stage[(buf * 3 + b) * BS + (e / N) * RS + (e % N)] = nx[b][k];
+      }
+  };
+  // operands of row rl of a staged block (see GramRow for the tile mapping)
+  auto operand = [&](const C_* blk, int rl, double (&v)[NT]) {
+    if constexpr (N == 16) {
+      C_ z = blk[rl * RS + c];
+      v[0] = (double)z.x;
+      v[1] = (double)z.y;
+    } else {
+      v[0] = (double)((const decltype(C_().x)*)(blk + rl * RS))[c];
+    }
+  };
+  int buf = 0;
+  if (rr.r0 < rr.r1) {
+    fetch(rr.r0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int r0 = rr.r0; r0 < rr.r1; r0 += GCH) {
+    const bool more = r0 + GCH < rr.r1;
+    if (more) fetch(r0 + GCH);
+    const C_* xs = stage + (buf * 3 + xb) * BS;
+    const C_* ys = stage + (buf * 3 + yb) * BS;
+#pragma unroll 2
+    for (int st = 0; st < GCH / 4; ++st) {
+      double x[NT], y[NT];
+      operand(xs, 4 * st + g, x);
+      if (sym) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) y[t] = x[t];
+      } else {
+        operand(ys, 4 * st + g, y);
+      }
+#pragma unroll
+      for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b)
+          if (!sym || b >= a)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // each wave's real Gram into LDS (tile row g + 4k, column c), then the
+  // complex entries of all four products
+  double* R = (double*)smem + wave * NR * NR;
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      if (sym && b < a) continue;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int i = a * 16 + g + 4 * k, j = b * 16 + c;
+        R[i * NR + j] = acc[a][b][k];
+        if (sym && a != b) R[j * NR + i] = acc[a][b][k];
+      }
+    }
+  __syncthreads();
+  double2* part = partials + (size_t)blockIdx.x * 4 * NN;
+  for (int e = tid; e < 4 * NN; e += BMS_WG) {
+    int gi = e / NN, ij = e - gi * NN;
+    int i = ij / N, j = ij - (ij / N) * N;
+    part[e] = GR::entry((const double*)smem + gi * NR * NR, i, j);
+  }
+  last_block_sum(partials, G4, 4 * NN, counter);
+}
+
 }  // namespace
 
 int gram4_tb(int n) { return (n >= 16 && n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1); }
@@ -623,14 +918,41 @@ bool gram4_fits(int n) {
   return 2 * nt * nt + nt * (nt + 1) <= BMS_WG;
 }
 
+bool gram4_mfma_supported(int n) { return n == 8 || n == 16; }
+
 template <typename T>
 hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const void* Q,
                         const void* W, double2* G4, double2* partials, int* counter, int nb,
-                        const int* skip) {
+                        const int* skip, int variant) {
   int per = rows_per_block(rows, nb);
   const cplx<T>* p = (const cplx<T>*)P;
   const cplx<T>* q = (const cplx<T>*)Q;
   const cplx<T>* w = (const cplx<T>*)W;
+  if (variant < 0 || variant == 3) {
+    if (n == 16) {
+      k_gram4_lds<T, 16><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+      return hipGetLastError();
+    }
+    if (n == 8) {
+      k_gram4_lds<T, 8><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+      return hipGetLastError();
+    }
+  }
+  if ((variant == 1 || variant == 2) && gram4_mfma_supported(n)) {
+    // variant 1: 4 steps in flight per wave, otherwise 8
+    if (n == 16) {
+      if (variant == 1)
+        k_gram4_mfma<T, 16, 4><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+      else
+        k_gram4_mfma<T, 16, 8><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+    } else {
+      if (variant == 1)
+        k_gram4_mfma<T, 8, 4><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+      else
+        k_gram4_mfma<T, 8, 8><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+    }
+    return hipGetLastError();
+  }
   if (!gram4_fits(n)) {  // four pairwise passes
     const cplx<T>* xs[4] = {p, q, w, q};
     const cplx<T>* ys[4] = {w, w, w, q};
@@ -653,9 +975,11 @@ hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const vo
   return hipGetLastError();
 }
 template hipError_t launch_gram4<double>(hipStream_t, int, int, const void*, const void*,
-                                         const void*, double2*, double2*, int*, int, const int*);
+                                         const void*, double2*, double2*, int*, int, const int*,
+                                         int);
 template hipError_t launch_gram4<float>(hipStream_t, int, int, const void*, const void*,
-                                        const void*, double2*, double2*, int*, int, const int*);
+                                        const void*, double2*, double2*, int*, int, const int*,
+                                        int);
 
 // ---- fused update, specialised on the block width ---------------------------
 // Same arithmetic as k_update. Thread (row lr, column j) of each of NCH chunks

@@ -54,10 +54,14 @@ __global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restri
 }
 
 // out(s) = b * sum_k L_k(s) in(nbr_k(s)) + a * aux(s) on n columns.
-// One thread per (site, group of R consecutive columns): the lanes of a site
-// share its links (the block operator reads each link once per n columns),
-// each link element is reused across the thread's R columns, and the R
-// columns of a neighbour are one contiguous run.
+// One thread per (site, column group g): the n/R threads of a site share its
+// links (the block operator reads each link once per n columns) and each link
+// element is reused across the thread's R columns g, g + n/R, g + 2n/R, ...
+// In FP64 the columns are interleaved this way, so that every load and store
+// instruction touches one contiguous run per site (the site's threads read
+// neighbouring columns) and a wave touches as few cache lines as the bytes
+// allow. In FP32 a thread's R columns are consecutive instead (g*R .. g*R+R-1),
+// which the compiler loads as 16-byte vectors.
 template <typename T, int R>
 __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ links,
                                                 const cplx<T>* __restrict__ in,
@@ -71,7 +75,9 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
   uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
   if (tid >= (uint32_t)g.vh * ngrp) return;
   uint32_t s = fdiv(tid, dgrp);
-  int j0 = (int)(tid - s * ngrp) * R;
+  constexpr bool kInterleave = sizeof(T) == 8;
+  const int cstep = kInterleave ? (int)ngrp : 1;  // column stride of a thread
+  const int j0 = (int)(tid - s * ngrp) * (kInterleave ? 1 : R);  // its first column
   SiteCoord c = site_coords(s, g, par);
   C acc[3][R];
 #pragma unroll
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
     for (int cb = 0; cb < 3; ++cb) {
       C v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = src[cb * n + r];
+      for (int r = 0; r < R; ++r) v[r] = src[cb * n + r * cstep];
 #pragma unroll
       for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
   for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      size_t oo = o + a3 * n + r;
+      size_t oo = o + a3 * n + r * cstep;
       out[oo] = aux ? cadd(cscale(aux[oo], a), cscale(acc[a3][r], b)) : cscale(acc[a3][r], b);
     }
 }

@@ -38,12 +38,14 @@ struct bms_ctx {
   hipStream_t stream = nullptr;  // library-owned work stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int device = -1;
+  int num_cu = 0;  // compute units of the device (set with the stream)
   bool gauge_set = false;
   DevBuf links64, links32;  // [parity][blocked links] complex
   std::vector<DevBuf> scratch;  // named by slot index
   std::string last_error;
   // kernel variants (bms_set_variant); -1 = built-in default
   int update_variant = -1;
+  int gram_variant = -1;
   // per-kernel timing (bms_timing_enable)
   bool timing = false;
   double kt_ms[BMS_NKERNELS] = {0};
@@ -87,7 +89,7 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
 template <typename T>
 hipError_t launch_gram(hipStream_t st, int rows, int n, const void* X, const void* Y, double2* G,
                        double2* partials, int* counter, int nb, const int* skip);
-int gram_blocks(int rows, int n);
+int gram_blocks(int rows, int n, int num_cu);
 
 // Y = X M (rows x n times n x n, M FP64 on device), optionally Y += (accum)
 template <typename T>

@@ -25,8 +25,6 @@
 #include <numeric>
 #include <vector>
 
-#include <type_traits>
-
 #include "blas.h"
 
 namespace {
@@ -120,7 +118,7 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   w.Gtmp = d;
   d += nn;
   w.sm.norm0 = (double*)d;
-  w.nb = gram_blocks(w.rows, n);
+  w.nb = gram_blocks(w.rows, n, c->num_cu);
   void* pp;
   if ((rc = scratch_buf(c, S_PART, part_bytes(w.nb, 4 * nn), &pp))) return rc;
   w.partials = (double2*)pp;
@@ -156,7 +154,7 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   HIP_TRY(c, launch_hop<T>(c, 0, w.n, w.W1, w.W, P0, mass * mass + sp.sigma[0], -1.0, skip));
   MARK(2);
   HIP_TRY(c, launch_gram4<T>(c->stream, w.rows, w.n, P0, w.Q, w.W, w.sm.G4, w.partials,
-                             w.counters, w.nb, skip));
+                             w.counters, w.nb, skip, c->gram_variant));
   MARK(3);
   HIP_TRY(c, launch_small_iter<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mx,
                                   (cplx<T>*)w.Mp));
@@ -182,17 +180,13 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   ua.Mp = (const cplx<T>*)w.Mp;
   ua.flags = w.flags;
   for (int s = 0; s < BMS_MAX_SHIFTS; ++s) ua.xidx[s] = s < w.ns ? s : 0;
-  // built-in default: the matrix-core kernel in FP64 where it exists, else
+  // built-in default: the matrix-core kernel where it exists (n = 8, 16), else
   // four row chunks with one coefficient column at a time
   const int uv = c->update_variant;
-  bool on_mfma = false;
-  if constexpr (std::is_same<T, double>::value) {
-    if (update_mfma_supported(w.n) && (uv < 0 || uv == 4)) {
-      HIP_TRY(c, launch_update_mfma(c->stream, ua));
-      on_mfma = true;
-    }
-  }
-  if (!on_mfma) HIP_TRY(c, (launch_update_fast<T, T>(c->stream, ua, uv < 0 || uv == 4 ? 2 : uv)));
+  if (update_mfma_supported(w.n) && (uv < 0 || uv >= 4))
+    HIP_TRY(c, launch_update_mfma<T>(c->stream, ua, uv == 5));
+  else
+    HIP_TRY(c, (launch_update_fast<T, T>(c->stream, ua, uv < 0 || uv >= 4 ? 2 : uv)));
   MARK(7);
 #undef MARK
   return BMS_OK;
@@ -362,7 +356,7 @@ static int residual_norms(bms_ctx* c, double mass, int n, int ns, const double* 
   if ((rc = scratch_buf(c, S_R1, blk * sizeof(double2), &t1))) return rc;
   if ((rc = scratch_buf(c, S_R2, blk * sizeof(double2), &t2))) return rc;
   if ((rc = scratch_buf(c, S_RES, (size_t)ns * n * sizeof(double2) + 64, &out))) return rc;
-  int nb = gram_blocks(rows, n);
+  int nb = gram_blocks(rows, n, c->num_cu);
   void* pp;
   if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
   void* fp;
@@ -573,7 +567,7 @@ extern "C" int bms_action(bms_ctx* c, int n, int ns, double a0, const double* al
   if ((rc = scratch_buf(c, S_RES, (size_t)(n + BMS_MAX_SHIFTS) * sizeof(double2) + 64, &out)))
     return rc;
   al = (double2*)out + n;
-  int nb = gram_blocks(rows, n);
+  int nb = gram_blocks(rows, n, c->num_cu);
   if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
   if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
   int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2 * CNT_STRIDE;

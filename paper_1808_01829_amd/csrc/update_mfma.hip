@@ -1,23 +1,26 @@
-// FP64 fused block update on the matrix cores (v_mfma_f64_16x16x4).
+// Fused block update on the matrix cores (v_mfma_f64_16x16x4 in FP64,
+// v_mfma_f32_16x16x4 for the shift updates of the mixed solver).
 //
 // Same arithmetic as the vector update kernels, per iteration k of
 // Algorithm 1 (block CG with Cholesky-QR, Sec. III):
 //   Q_{k+1} = (Q_k - W alpha_k) rho_k^-1   computed as  Q_k rho^-1 + W (-alpha rho^-1)
 //   X^(s)  += P^(s) Mx^(s)                 (Mx = alpha^(s)_k)
 //   P^(s)   = Q_{k+1} + P^(s) Mp^(s)       (Mp = beta^(s)_k rho_k^dag)
-// for every shift still active.
+// for every shift still active. The Q step always runs in FP64 (FP32 blocks
+// are widened on load), the shift updates in the block precision.
 //
 // A complex row of n entries is 2n interleaved reals; a right product with a
 // complex n x n matrix M is the real product with the 2n x 2n matrix
 //   [ Re M  Im M ]
 //   [-Im M  Re M ]   (rows in (re, im) pairs, columns permuted: all real parts
 // first, then all imaginary parts). Each wave owns 16-row tiles. The MFMA
-// operand layouts (A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j]
-// in lane j + 16(i%4), element i/4; the D layout was measured on gfx950) give:
+// operand layouts (A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the
+// accumulator D[i][j] in lane j + 16(i%4), element i/4 for f64 and in lane
+// j + 16(i/4), element i%4 for f32 -- both measured on gfx950) give:
 //   A operand: lane (g = lane/16, c = lane%16) holds row c, reals g*KS .. g*KS+KS-1
 //              (the contraction order is free, so each lane reads one contiguous run);
-//   D: lane (g, c) holds rows g, g+4, g+8, g+12 at real output column nt*16 + c, which for
-//      n = 16 is (Re, Im) of complex column c in the two n-tiles: one 16-byte
+//   D: lane (g, c) holds four rows of the tile at real output column nt*16 + c,
+//      which for n = 16 is (Re, Im) of complex column c in the two n-tiles: one
 //      complex per row, so X and P are read and written as whole complex numbers.
 // The coefficient matrices are expanded into that B layout in LDS once per
 // work-group and shift (double-buffered, one barrier per shift).
@@ -26,15 +29,36 @@
 namespace {
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
 
 constexpr int MF_WAVES = BMS_WG / 64;
+
+template <typename F>
+struct Mf;
+template <>
+struct Mf<double> {
+  using V = dx4;
+  __device__ static __forceinline__ V mfma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // tile row of accumulator element p in lane group g
+  __device__ static __forceinline__ int row(int g, int p) { return g + 4 * p; }
+};
+template <>
+struct Mf<float> {
+  using V = fx4;
+  __device__ static __forceinline__ V mfma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int g, int p) { return 4 * g + p; }
+};
 
 template <int N>
 struct MfShape {
   static constexpr int NR = 2 * N;      // reals per row
   static constexpr int KS = NR / 4;     // k-steps of 4
   static constexpr int NT = NR / 16;    // 16-column output tiles
-  static constexpr int BSZ = NR * NR;   // doubles of one expanded matrix
+  static constexpr int BSZ = NR * NR;   // reals of one expanded matrix
 };
 
 // entry (kk, flat) of the expanded matrix -> its LDS slot in B-operand order
@@ -47,16 +71,16 @@ __device__ __forceinline__ int bslot(int kk, int flat) {
 }
 
 // expand complex m = M[k][j] into the four reals it contributes
-template <int N>
-__device__ __forceinline__ void bput(double* B, int k, int j, double2 m) {
-  B[bslot<N>(2 * k, j)] = m.x;
-  B[bslot<N>(2 * k, N + j)] = m.y;
-  B[bslot<N>(2 * k + 1, j)] = -m.y;
-  B[bslot<N>(2 * k + 1, N + j)] = m.x;
+template <int N, typename F>
+__device__ __forceinline__ void bput(F* B, int k, int j, double2 m) {
+  B[bslot<N>(2 * k, j)] = (F)m.x;
+  B[bslot<N>(2 * k, N + j)] = (F)m.y;
+  B[bslot<N>(2 * k + 1, j)] = (F)-m.y;
+  B[bslot<N>(2 * k + 1, N + j)] = (F)m.x;
 }
 
-template <int N>
-__device__ __forceinline__ void bload(const double* B, int lane, double (&b)[MfShape<N>::KS][MfShape<N>::NT]) {
+template <int N, typename F>
+__device__ __forceinline__ void bload(const F* B, int lane, F (&b)[MfShape<N>::KS][MfShape<N>::NT]) {
   using S = MfShape<N>;
 #pragma unroll
   for (int ks = 0; ks < S::KS; ++ks)
@@ -64,183 +88,236 @@ __device__ __forceinline__ void bload(const double* B, int lane, double (&b)[MfS
     for (int nt = 0; nt < S::NT; ++nt) b[ks][nt] = B[(ks * 64 + lane) * S::NT + nt];
 }
 
-// A-operand reals of one tile row: row r, reals g*KS .. g*KS+KS-1
-template <int N>
-__device__ __forceinline__ void aload(const double2* base, int r, int rows, int g,
-                                      double (&a)[MfShape<N>::KS]) {
+// A-operand reals of one tile row (row r, reals g*KS .. g*KS+KS-1) in the
+// arithmetic type F. Rows past the end read row 0 and are zeroed, with no
+// branch around the loads (so the loads of several tiles stay in flight).
+template <int N, typename F, typename C>
+__device__ __forceinline__ void aload(const C* base, int r, int rows, int g,
+                                      F (&a)[MfShape<N>::KS]) {
   using S = MfShape<N>;
-  if (r < rows) {
-    const double2* p = base + (size_t)r * N + g * (S::KS / 2);
+  const bool ok = r < rows;
+  const C* p = base + (size_t)(ok ? r : 0) * N + g * (S::KS / 2);
 #pragma unroll
-    for (int h = 0; h < S::KS / 2; ++h) {
-      double2 v = p[h];
-      a[2 * h] = v.x;
-      a[2 * h + 1] = v.y;
-    }
-  } else {
-#pragma unroll
-    for (int h = 0; h < S::KS; ++h) a[h] = 0.0;
+  for (int h = 0; h < S::KS / 2; ++h) {
+    C v = p[h];
+    a[2 * h] = ok ? (F)v.x : (F)0;
+    a[2 * h + 1] = ok ? (F)v.y : (F)0;
   }
 }
 
-// D-layout access: lane (g, c), element p is row g+4p of the tile, output
+// D-layout access: lane (g, c), element p is tile row Mf<F>::row(g, p), output
 // real column flat = nt*16 + c: part flat / N (0 = re, 1 = im) of complex column flat % N.
-template <int N>
-__device__ __forceinline__ void dload(const double2* base, int r0, int rows, int g, int c,
-                                      dx4 (&d)[MfShape<N>::NT]) {
-  if constexpr (N == 16) {
+template <int N, typename F, typename C>
+__device__ __forceinline__ void dload(const C* base, int r0, int rows, int g, int c,
+                                      typename Mf<F>::V (&d)[MfShape<N>::NT]) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      int r = r0 + g + 4 * p;
-      double2 v = r < rows ? base[(size_t)r * N + c] : make_double2(0.0, 0.0);
-      d[0][p] = v.x;
-      d[1][p] = v.y;
-    }
-  } else {
-    const double* b = (const double*)base;
-    const int re = 2 * (c % N) + c / N;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      int r = r0 + g + 4 * p;
-      d[0][p] = r < rows ? b[(size_t)r * 2 * N + re] : 0.0;
+  for (int p = 0; p < 4; ++p) {
+    const int r = r0 + Mf<F>::row(g, p);
+    const bool ok = r < rows;
+    const size_t rr = ok ? (size_t)r : 0;
+    if constexpr (N == 16) {
+      C v = base[rr * N + c];
+      d[0][p] = ok ? (F)v.x : (F)0;
+      d[1][p] = ok ? (F)v.y : (F)0;
+    } else {
+      auto v = ((const decltype(C().x)*)base)[rr * 2 * N + 2 * (c % N) + c / N];
+      d[0][p] = ok ? (F)v : (F)0;
     }
   }
 }
 
-template <int N>
-__device__ __forceinline__ void dstore(double2* base, int r0, int rows, int g, int c,
-                                       const dx4 (&d)[MfShape<N>::NT]) {
-  if constexpr (N == 16) {
+template <int N, typename F, typename C>
+__device__ __forceinline__ void dstore(C* base, int r0, int rows, int g, int c,
+                                       const typename Mf<F>::V (&d)[MfShape<N>::NT]) {
+  using R = decltype(C().x);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      int r = r0 + g + 4 * p;
-      if (r < rows) base[(size_t)r * N + c] = make_double2(d[0][p], d[1][p]);
-    }
-  } else {
-    double* b = (double*)base;
-    const int re = 2 * (c % N) + c / N;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      int r = r0 + g + 4 * p;
-      if (r < rows) b[(size_t)r * 2 * N + re] = d[0][p];
+  for (int p = 0; p < 4; ++p) {
+    const int r = r0 + Mf<F>::row(g, p);
+    if (r >= rows) continue;
+    if constexpr (N == 16) {
+      C v;
+      v.x = (R)d[0][p];
+      v.y = (R)d[1][p];
+      base[(size_t)r * N + c] = v;
+    } else {
+      ((R*)base)[(size_t)r * 2 * N + 2 * (c % N) + c / N] = (R)d[0][p];
     }
   }
 }
 
-template <int N>
-__device__ __forceinline__ void mfma_acc(dx4 (&d)[MfShape<N>::NT], const double (&a)[MfShape<N>::KS],
-                                         const double (&b)[MfShape<N>::KS][MfShape<N>::NT]) {
+template <int N, typename F>
+__device__ __forceinline__ void mfma_acc(typename Mf<F>::V (&d)[MfShape<N>::NT],
+                                         const F (&a)[MfShape<N>::KS],
+                                         const F (&b)[MfShape<N>::KS][MfShape<N>::NT]) {
   using S = MfShape<N>;
 #pragma unroll
   for (int ks = 0; ks < S::KS; ++ks)
 #pragma unroll
-    for (int nt = 0; nt < S::NT; ++nt)
-      d[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks][nt], d[nt], 0, 0, 0);
+    for (int nt = 0; nt < S::NT; ++nt) d[nt] = Mf<F>::mfma(a[ks], b[ks][nt], d[nt]);
 }
 
-// T: 16-row tiles per wave (processed one after the other inside each shift,
-// so the coefficient operands are read from LDS once per wave and shift).
-template <int N, int T>
-__global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<double, double> a) {
+// F: block and shift-update arithmetic type (double, or float in the mixed
+// solver). NTILE: 16-row tiles per wave (processed one after the other inside
+// each shift, so the coefficient operands are read from LDS once per wave and
+// shift). The active shifts come from one ballot; the P^(s), X^(s) tiles of
+// the next active shift are loaded into the registers the current tile has
+// just stored from, so they are in flight during the next shift's expansion
+// and barrier.
+template <typename F, int N, int NTILE>
+__global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
   using S = MfShape<N>;
-  __shared__ double bl[2][2][S::BSZ];
+  using CF = cplx<F>;
+  using VF = typename Mf<F>::V;
+  // LDS: the Q-step operands (FP64) and the complex staging, then (FP32) the
+  // per-wave layout change of Q, then the double-buffered shift operands (F)
+  constexpr int QBYTES = 2 * S::BSZ * 8 + 2 * N * N * 16;
+  constexpr int TBYTES = MF_WAVES * NTILE * 16 * S::NR * 8;
+  constexpr int SBYTES = 2 * 2 * S::BSZ * (int)sizeof(F);
+  constexpr int LBYTES = QBYTES > SBYTES ? (QBYTES > TBYTES ? QBYTES : TBYTES)
+                                         : (SBYTES > TBYTES ? SBYTES : TBYTES);
+  __shared__ __align__(16) unsigned char lds[LBYTES];
+  double* qb0 = (double*)lds;
+  double* qb1 = qb0 + S::BSZ;
+  double2* cs = (double2*)(qb1 + S::BSZ);  // alpha, rho^-1
+  F* sb = (F*)lds;                         // [2][2][BSZ]
   const SolverFlags* fl = a.flags;
   if (fl->halted) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int rows = a.rows, ns = a.ns;
-  const int tile0 = (blockIdx.x * MF_WAVES + wave) * T;
-  const double2* Mx = (const double2*)a.Mx;
-  const double2* Mp = (const double2*)a.Mp;
+  const int tile0 = (blockIdx.x * MF_WAVES + wave) * NTILE;
+  unsigned long long mask = __ballot(lane < ns && fl->active[lane] != 0);
 
   // coefficients of the Q step: B0 = rho^-1, B1 = -alpha rho^-1
-  {
-    double2* cs = (double2*)&bl[1][0][0];  // complex staging: alpha, rho^-1
-    for (int e = tid; e < N * N; e += BMS_WG) {
-      cs[e] = a.alpha[e];
-      cs[N * N + e] = a.rhoinv[e];
-    }
-    __syncthreads();
-    for (int e = tid; e < N * N; e += BMS_WG) {
-      int i = e / N, j = e - (e / N) * N;
-      double2 t = make_double2(0.0, 0.0);
-      for (int k = 0; k < N; ++k) t = cfma(cs[i * N + k], cs[N * N + k * N + j], t);
-      bput<N>(bl[0][0], i, j, cs[N * N + e]);
-      bput<N>(bl[0][1], i, j, make_double2(-t.x, -t.y));
-    }
-    __syncthreads();
+  for (int e = tid; e < N * N; e += BMS_WG) {
+    cs[e] = a.alpha[e];
+    cs[N * N + e] = a.rhoinv[e];
   }
-  dx4 qn[T][S::NT];
+  __syncthreads();
+  for (int e = tid; e < N * N; e += BMS_WG) {
+    int i = e / N, j = e - (e / N) * N;
+    double2 t = make_double2(0.0, 0.0);
+    for (int k = 0; k < N; ++k) t = cfma(cs[i * N + k], cs[N * N + k * N + j], t);
+    bput<N>(qb0, i, j, cs[N * N + e]);
+    bput<N>(qb1, i, j, make_double2(-t.x, -t.y));
+  }
+  __syncthreads();
+  dx4 qd[NTILE][S::NT];
   {
     double b0[S::KS][S::NT], b1[S::KS][S::NT];
-    bload<N>(bl[0][0], lane, b0);
-    bload<N>(bl[0][1], lane, b1);
+    double av[NTILE][S::KS], wv[NTILE][S::KS];
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < NTILE; ++t) {
       const int r0 = (tile0 + t) * 16;
-      double av[S::KS];
+      aload<N>(a.Q, r0 + c, rows, g, av[t]);
+      aload<N>(a.W, r0 + c, rows, g, wv[t]);
+    }
+    bload<N>(qb0, lane, b0);
+    bload<N>(qb1, lane, b1);
 #pragma unroll
-      for (int nt = 0; nt < S::NT; ++nt) qn[t][nt] = dx4{0.0, 0.0, 0.0, 0.0};
-      if (r0 < rows) {
-        aload<N>(a.Q, r0 + c, rows, g, av);
-        mfma_acc<N>(qn[t], av, b0);
-        aload<N>(a.W, r0 + c, rows, g, av);
-        mfma_acc<N>(qn[t], av, b1);
-      }
+    for (int t = 0; t < NTILE; ++t) {
+#pragma unroll
+      for (int nt = 0; nt < S::NT; ++nt) qd[t][nt] = dx4{0.0, 0.0, 0.0, 0.0};
+      mfma_acc<N>(qd[t], av[t], b0);
+      mfma_acc<N>(qd[t], wv[t], b1);
     }
   }
   // every lane of the wave has read its Q tiles before any is overwritten
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int r0 = (tile0 + t) * 16;
-    if (r0 < rows) dstore<N>(a.Q, r0, rows, g, c, qn[t]);
+  for (int t = 0; t < NTILE; ++t) dstore<N, double>(a.Q, (tile0 + t) * 16, rows, g, c, qd[t]);
+  __syncthreads();  // the Q-step LDS is reused below
+  // Q_{k+1} in the shift-update layout and precision: the same registers in
+  // FP64; in FP32 rounded and moved to the f32 row mapping through LDS
+  VF qn[NTILE][S::NT];
+  if constexpr (sizeof(F) == 8) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int nt = 0; nt < S::NT; ++nt) qn[t][nt] = qd[t][nt];
+  } else {
+    double* tq = (double*)lds + wave * (NTILE * 16 * S::NR);
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int nt = 0; nt < S::NT; ++nt)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          tq[(t * 16 + Mf<double>::row(g, p)) * S::NR + nt * 16 + c] = qd[t][nt][p];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int nt = 0; nt < S::NT; ++nt)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          qn[t][nt][p] = (F)tq[(t * 16 + Mf<F>::row(g, p)) * S::NR + nt * 16 + c];
+    __syncthreads();  // the shift operands overwrite this LDS
   }
-  __syncthreads();  // bl[0] is rewritten below
 
+  F pa[NTILE][S::KS];
+  VF xa[NTILE][S::NT];
+  int s = mask ? __ffsll((long long)mask) - 1 : -1;
+  if (s >= 0) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) {
+      const int r0 = (tile0 + t) * 16;
+      aload<N>(a.P + (size_t)s * rows * N, r0 + c, rows, g, pa[t]);
+      dload<N, F>(a.X + (size_t)a.xidx[s] * rows * N, r0, rows, g, c, xa[t]);
+    }
+  }
   int buf = 0;
-  for (int s = 0; s < ns; ++s) {
-    if (!fl->active[s]) continue;
-    double* bx = bl[buf][0];
-    double* bp = bl[buf][1];
-    const double2* mx = Mx + (size_t)s * N * N;
-    const double2* mp = Mp + (size_t)s * N * N;
+  while (s >= 0) {
+    mask &= mask - 1;
+    const int s2 = mask ? __ffsll((long long)mask) - 1 : -1;
+    F* bx = sb + (2 * buf) * S::BSZ;
+    F* bp = bx + S::BSZ;
+    const CF* mx = a.Mx + (size_t)s * N * N;
+    const CF* mp = a.Mp + (size_t)s * N * N;
     for (int e = tid; e < N * N; e += BMS_WG) {
       int i = e / N, j = e - (e / N) * N;
-      bput<N>(bx, i, j, mx[e]);
-      bput<N>(bp, i, j, mp[e]);
+      bput<N>(bx, i, j, to_d(mx[e]));
+      bput<N>(bp, i, j, to_d(mp[e]));
     }
     __syncthreads();
-    double cx[S::KS][S::NT], cp[S::KS][S::NT];
+    F cx[S::KS][S::NT], cp[S::KS][S::NT];
     bload<N>(bx, lane, cx);
     bload<N>(bp, lane, cp);
-    double2* P = a.P + (size_t)s * rows * N;
-    double2* X = a.X + (size_t)a.xidx[s] * rows * N;
+    CF* P = a.P + (size_t)s * rows * N;
+    CF* X = a.X + (size_t)a.xidx[s] * rows * N;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < NTILE; ++t) {
       const int r0 = (tile0 + t) * 16;
-      if (r0 >= rows) break;
-      double pa[S::KS];
-      dx4 xa[S::NT], pn[S::NT];
-      aload<N>(P, r0 + c, rows, g, pa);
-      dload<N>(X, r0, rows, g, c, xa);
-      mfma_acc<N>(xa, pa, cx);
+      VF pn[S::NT], dx[S::NT];
 #pragma unroll
-      for (int nt = 0; nt < S::NT; ++nt) pn[nt] = qn[t][nt];
-      mfma_acc<N>(pn, pa, cp);
-      dstore<N>(X, r0, rows, g, c, xa);
-      dstore<N>(P, r0, rows, g, c, pn);
+      for (int nt = 0; nt < S::NT; ++nt) {
+        pn[nt] = qn[t][nt];
+        dx[nt] = VF{0, 0, 0, 0};
+      }
+      // the increment P^(s) Mx is formed on its own and added to X once, so
+      // X (large next to one step's increment) is rounded once per iteration
+      mfma_acc<N>(dx, pa[t], cx);
+      mfma_acc<N>(pn, pa[t], cp);
+#pragma unroll
+      for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
+      dstore<N, F>(X, r0, rows, g, c, xa[t]);
+      dstore<N, F>(P, r0, rows, g, c, pn);
+      if (s2 >= 0) {
+        aload<N>(a.P + (size_t)s2 * rows * N, r0 + c, rows, g, pa[t]);
+        dload<N, F>(a.X + (size_t)a.xidx[s2] * rows * N, r0, rows, g, c, xa[t]);
+      }
     }
+    s = s2;
     buf ^= 1;
   }
 }
 
-template <int N, int T>
-hipError_t launch_mf(hipStream_t st, const UpdateArgs<double, double>& a) {
+template <typename F, int N, int NTILE>
+hipError_t launch_mf(hipStream_t st, const UpdateArgs<F, F>& a) {
   int tiles = (a.rows + 15) / 16;
-  int waves = (tiles + T - 1) / T;
+  int waves = (tiles + NTILE - 1) / NTILE;
   int blocks = (waves + MF_WAVES - 1) / MF_WAVES;
-  k_update_mfma<N, T><<<blocks, BMS_WG, 0, st>>>(a);
+  k_update_mfma<F, N, NTILE><<<blocks, BMS_WG, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -248,10 +325,16 @@ hipError_t launch_mf(hipStream_t st, const UpdateArgs<double, double>& a) {
 
 bool update_mfma_supported(int n) { return n == 8 || n == 16; }
 
-hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<double, double>& a) {
+// two_tiles: two 16-row tiles per wave instead of one
+template <typename F>
+hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<F, F>& a, bool two_tiles) {
   switch (a.n) {
-    case 16: return launch_mf<16, 2>(st, a);
-    case 8: return launch_mf<8, 2>(st, a);
+    case 16: return two_tiles ? launch_mf<F, 16, 2>(st, a) : launch_mf<F, 16, 1>(st, a);
+    case 8: return two_tiles ? launch_mf<F, 8, 2>(st, a) : launch_mf<F, 8, 1>(st, a);
     default: return hipErrorInvalidValue;
   }
 }
+
+template hipError_t launch_update_mfma<double>(hipStream_t, const UpdateArgs<double, double>&,
+                                               bool);
+template hipError_t launch_update_mfma<float>(hipStream_t, const UpdateArgs<float, float>&, bool);
