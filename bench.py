@@ -7,10 +7,16 @@ all shifts of the rational approximation to a true FP64 relative residual
 time, inputs resident in HBM. Printed as one JSON line, with:
   roofline      the dominant kernel's algorithmic GB/s (HIP events around each
                 launch on the library stream, summed over the timed steps)
-                against the 8 TB/s HBM peak
+                against the 8 TB/s HBM peak; traffic = measured HBM bytes per
+                launch from the committed rocprofv3 counter summary of that
+                kernel (profiles/traffic_<workload>_<precision>.json), null when
+                the kernel's source changed since the counters were taken
   per_vector    the same library at n = 1 in FP64 (multi-shift CG per column)
+  other_precision  the same solve in the other precision (FP64 <-> mixed)
   cpu_baseline  the FP64 CPU oracle's multi-shift CG on a bounded sample
+The precision of the timed solves is the workload's (mixed at 32^4).
 """
+import hashlib
 import argparse
 import json
 import os
@@ -56,6 +62,32 @@ def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s):
                            per_vector_iters)))
 
 
+# source file of each kernel class (for the staleness check of stored counters)
+KERNEL_SOURCE = {"update": "paper_1808_01829_amd/csrc/update_mfma.hip",
+                 "hop": "paper_1808_01829_amd/csrc/hop.hip",
+                 "gram": "paper_1808_01829_amd/csrc/blas.hip"}
+
+
+def source_sha(kernel):
+    path = os.path.join(ROOT, KERNEL_SOURCE.get(kernel, ""))
+    if not os.path.isfile(path):
+        return None
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def stored_traffic(workload, prec, kernel):
+    """Measured HBM bytes per launch of `kernel` from the committed counter
+    summary, or None if there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, prec))
+    if not os.path.isfile(path):
+        return None
+    d = json.load(open(path))
+    k = d.get("kernels", {}).get(kernel)
+    if not k or k.get("source_sha256") != source_sha(kernel):
+        return None
+    return k.get("bytes_per_launch")
+
+
 def per_vector(ctx, bms, m, r, Bd, tol, cols, torch):
     """Same library, n = 1, FP64, one column at a time (multi-shift CG)."""
     iters = []
@@ -97,7 +129,7 @@ def main():
 
     w = configs.WORKLOADS[args.workload]
     r = configs.workload_coefficients(args.workload)
-    prec = args.precision or "f64"
+    prec = args.precision or w["precision"]
     dims, n, m, tol = w["dims"], w["n"], w["mass"], w["tol"]
     log("bench: workload %s dims %s n %d shifts %d precision %s" % (args.workload, dims, n,
                                                                      r.n_poles, prec))
@@ -145,12 +177,14 @@ def main():
     kernels = {}
     for name, (ms, nl, by) in kt.items():
         if nl:
-            kernels[name] = dict(ms_total=ms, launches=nl, avg_us=1e3 * ms / nl,
+            kernels[name] = dict(ms_total=ms, launches=nl, avg_us=1e3 * ms / nl, bytes=by,
                                  gbs=(by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None)
     dom = max((k for k in kernels if kernels[k]["gbs"]), key=lambda k: kernels[k]["ms_total"])
     dk = kernels[dom]
     roofline = dict(bound="hbm", kernel=dom, achieved=round(dk["gbs"], 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None)
+                    unit="GB/s", frac=round(dk["gbs"] / HBM_PEAK_GBS, 4),
+                    traffic=stored_traffic(args.workload, prec, dom),
+                    algorithmic_bytes_per_launch=round(dk["bytes"] / dk["launches"]))
 
     # per-vector baseline: same library, n = 1, FP64, one column at a time
     pv_iters = [0]
