@@ -221,8 +221,10 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  * 1 and 2 = the matrix-core kernel (n = 8 and 16, FP32 or FP64 inputs, FP64
  * accumulation) with 4 or 8 row steps in flight per wave, 0 = the vector
  * kernel, -1 = the default (2 where it applies).
- * Other kernels are rejected with BMS_EINVAL; other widths and precisions
- * ignore the setting. Results do not depend on the variant beyond rounding
+ * For BMS_KERNEL_HOP: 1 = four threads per site sharing the site's links
+ * (n = 4, 8, 16, 32), 0 = one thread per site and column group, -1 = the
+ * default (1 where it applies, except FP32 at n = 16). Other kernels are rejected with BMS_EINVAL;
+ * other widths and precisions ignore the setting. Results do not depend on the variant beyond rounding
  * order.
  */
 int bms_set_variant(bms_ctx* ctx, int kernel, int variant);

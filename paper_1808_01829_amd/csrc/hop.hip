@@ -115,6 +115,91 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
     }
 }
 
+// Broadcast a value from lane Q of each group of four lanes to the whole group
+// (DPP quad permute [Q, Q, Q, Q]).
+template <int Q>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), Q * 0x55,
+                                                              0xF, 0xF, false));
+}
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v) {
+  long long u = __builtin_bit_cast(long long, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)u, Q * 0x55, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), Q * 0x55, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The same half hop with four threads per site (n = 4R columns) that share
+// the site's links: for each hop, thread q of the site loads link elements q,
+// q+4 (and thread 0 element 8), a third of the link load instructions, and
+// element e reaches the other three threads of the quad by a DPP broadcast
+// from lane e % 4. Columns as in k_hop (interleaved in FP64, consecutive in
+// FP32).
+template <typename T, int R>
+__global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ links,
+                                                  const cplx<T>* __restrict__ in,
+                                                  cplx<T>* __restrict__ out,
+                                                  const cplx<T>* __restrict__ aux, T a, T b,
+                                                  Geom g, int n, int par, int sbl,
+                                                  const int* __restrict__ skip) {
+  using C = cplx<T>;
+  if (skip && *skip) return;
+  const uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
+  // whole quads leave together (4 * Vh threads), so every DPP source lane is active
+  if (tid >= (uint32_t)g.vh * 4) return;
+  const uint32_t s = tid >> 2;
+  const int q = (int)(tid & 3);
+  constexpr bool kInterleave = sizeof(T) == 8;
+  const int cstep = kInterleave ? 4 : 1;
+  const int j0 = kInterleave ? q : q * R;
+  const int e2 = q == 0 ? 8 : q + 4;  // thread 0 also fetches element 8 (others repeat q+4)
+  SiteCoord c = site_coords(s, g, par);
+  C acc[3][R];
+#pragma unroll
+  for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
+  const size_t st = (size_t)1 << sbl;
+#pragma unroll 2
+  for (int k = 0; k < 8; ++k) {
+    const int mu = k & 3;
+    const int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
+    const C* src = in + (size_t)nb * 3 * n + j0;
+    const C* L = links + link_off(s, k, 0, sbl);
+    const C t0 = L[q * st], t1 = L[(q + 4) * st], t2 = L[e2 * st];
+    C l[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      const C own = e < 4 ? t0 : (e < 8 ? t1 : t2);
+      switch (e & 3) {
+        case 0: l[e].x = quad_bcast<0>(own.x); l[e].y = quad_bcast<0>(own.y); break;
+        case 1: l[e].x = quad_bcast<1>(own.x); l[e].y = quad_bcast<1>(own.y); break;
+        case 2: l[e].x = quad_bcast<2>(own.x); l[e].y = quad_bcast<2>(own.y); break;
+        default: l[e].x = quad_bcast<3>(own.x); l[e].y = quad_bcast<3>(own.y);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb) {
+      C v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[cb * n + r * cstep];
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[r], acc[a3][r]);
+    }
+  }
+  const size_t o = (size_t)s * 3 * n + j0;
+#pragma unroll
+  for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      size_t oo = o + a3 * n + r * cstep;
+      out[oo] = aux ? cadd(cscale(aux[oo], a), cscale(acc[a3][r], b)) : cscale(acc[a3][r], b);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32) {
@@ -132,6 +217,25 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   const DevBuf& lb = sizeof(T) == 8 ? c->links64 : c->links32;
   size_t pstride = (size_t)c->nblk * 72 << c->sbl;
   const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
+  // four threads per site sharing the links, for n = 4, 8, 16, 32; by default
+  // not for FP32 at n = 16, where the consecutive-column kernel measured faster
+  const bool quad_default = !(sizeof(T) == 4 && n == 16);
+  if ((c->hop_variant == 1 || (c->hop_variant < 0 && quad_default)) &&
+      (n == 4 || n == 8 || n == 16 || n == 32)) {
+    dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);
+#define HOPQ(RR)                                                                           \
+  k_hop_q<T, RR><<<qgrid, BMS_WG, 0, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out, \
+                                                 (const cplx<T>*)aux, (T)a, (T)b, c->geom, \
+                                                 n, par, c->sbl, skip)
+    switch (n) {
+      case 4: HOPQ(1); break;
+      case 8: HOPQ(2); break;
+      case 16: HOPQ(4); break;
+      default: HOPQ(8);
+    }
+#undef HOPQ
+    return hipGetLastError();
+  }
   const int R = (n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1);
   uint32_t ngrp = (uint32_t)(n / R);
   uint32_t nthr = (uint32_t)c->vh * ngrp;

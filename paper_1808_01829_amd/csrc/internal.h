@@ -46,6 +46,7 @@ struct bms_ctx {
   // kernel variants (bms_set_variant); -1 = built-in default
   int update_variant = -1;
   int gram_variant = -1;
+  int hop_variant = -1;
   // per-kernel timing (bms_timing_enable)
   bool timing = false;
   double kt_ms[BMS_NKERNELS] = {0};

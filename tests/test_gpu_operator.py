@@ -36,12 +36,15 @@ def test_hop_f64_and_f32(torch, dims, n, bc):
     U = random_gauge(dims, 0.7, 101)
     c = _ctx(dims, bc, U)
     v = gaussian_block(dims, n, 102)
-    for par in (0, 1):
-        ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], axis=-1)
-        out = to_np(c.apply_hop(par, to_dev(torch, v)))
-        assert rel(out, ref) < 1e-13
-        out32 = to_np(c.apply_hop(par, to_dev(torch, v.astype(np.complex64)), bms.BMS_PREC_F32))
-        assert rel(out32, ref) < 2e-6
+    # default kernel, then the one-thread-per-column-group kernel (variant 0)
+    for variant in (-1, 0):
+        c.set_variant(bms.BMS_KERNEL_HOP, variant)
+        for par in (0, 1):
+            ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], axis=-1)
+            out = to_np(c.apply_hop(par, to_dev(torch, v)))
+            assert rel(out, ref) < 1e-13
+            out32 = to_np(c.apply_hop(par, to_dev(torch, v.astype(np.complex64)), bms.BMS_PREC_F32))
+            assert rel(out32, ref) < 2e-6
 
 
 @pytest.mark.parametrize("dims,n", CASES[:6])
