@@ -81,8 +81,9 @@ typedef struct bms_opts {
   int check_interval;     /* iterations between host-side convergence checks (8) */
   int max_refine;         /* MIXED: rounds of per-shift defect correction (4) */
   int qr_passes;          /* Cholesky-QR passes per iteration, 1 or 2 (1) */
-  int use_graph;          /* reserved: accepted and ignored (iteration chunks are
-                             launched directly on the stream) */
+  int use_graph;          /* replay each chunk of check_interval iterations from a
+                             captured hipGraph (1, default), or launch directly (0);
+                             chunks launch directly while timing is enabled */
 } bms_opts;
 
 /* Solver statistics (filled on BMS_OK, BMS_ENOCONV and BMS_EBREAKDOWN). */
@@ -228,6 +229,40 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  * order.
  */
 int bms_set_variant(bms_ctx* ctx, int kernel, int variant);
+
+/* The variant currently set for a kernel class (BMS_KERNEL_HOP, _GRAM, _UPDATE). */
+int bms_get_variant(const bms_ctx* ctx, int kernel, int* variant);
+
+/*
+ * Pick the fastest variant of the hop, Gram and update kernels for this
+ * context's lattice, block width n, shifts and precision (BMS_PREC_F64 or
+ * BMS_PREC_MIXED): one kernel class after another, every candidate is timed
+ * (HIP events on the library stream) over `iters` block iterations of a
+ * real solve of B, and the fastest is kept (see bms_set_variant). B as for
+ * bms_solve; X is a caller array of the bms_solve shape used as scratch (its
+ * contents are undefined afterwards). Results of later solves do not depend
+ * on the choice beyond rounding order. Errors: BMS_EINVAL for bad arguments
+ * (as bms_solve, plus iters outside [1, 4096]); the status of a failing solve
+ * otherwise.
+ */
+int bms_autotune(bms_ctx* ctx, double mass, int n, int n_shifts, const double* shifts,
+                 int precision, int iters, const void* B, void* X);
+
+/*
+ * A batch of independent solves, e.g. an uneven batch of gauge fields on
+ * different lattices: problem i is bms_solve(ctxs[i], mass[i], n[i],
+ * n_shifts[i], shifts[i], tol[i], max_iter[i], opts ? &opts[i] : NULL, B[i],
+ * X[i], stats ? &stats[i] : NULL), each on its own context (distinct
+ * contexts; each with its own library stream), all run at the same time from
+ * host threads so that the GPU overlaps them. status[i] receives problem i's
+ * status. Returns BMS_OK when every problem did, else the first failing
+ * problem's status; BMS_EINVAL (nothing run) for nprob outside [1, 64], a
+ * NULL array or context, or a context given twice. Blocks until all are done.
+ */
+int bms_solve_batch(int nprob, bms_ctx* const* ctxs, const double* mass, const int* n,
+                    const int* n_shifts, const double* const* shifts, const double* tol,
+                    const int* max_iter, const bms_opts* opts, const void* const* B,
+                    void* const* X, bms_stats* stats, int* status);
 int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,
                     double* bytes);
 

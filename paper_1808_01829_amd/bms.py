@@ -41,7 +41,8 @@ KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small"]
 
 EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create", "bms_destroy",
            "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",
-           "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant"]
+           "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant",
+           "bms_get_variant", "bms_autotune", "bms_solve_batch"]
 
 
 class bms_opts(ctypes.Structure):
@@ -93,6 +94,12 @@ def _lib():
         L.bms_timing_enable.argtypes = [vp, i]
         L.bms_set_variant.argtypes = [vp, i, i]
         L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
+        L.bms_get_variant.argtypes = [vp, i, ip]
+        L.bms_autotune.argtypes = [vp, d, i, i, dp, i, i, vp, vp]
+        L.bms_solve_batch.argtypes = [i, ctypes.POINTER(vp), dp, ip, ip,
+                                      ctypes.POINTER(dp), dp, ip, ctypes.POINTER(bms_opts),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(bms_stats), ip]
         for f in EXPORTS:
             if f not in ("bms_default_opts", "bms_error_string", "bms_last_error"):
                 getattr(L, f).restype = ctypes.c_int
@@ -211,6 +218,51 @@ def bms_set_variant(ctx, kernel, variant):
     _check(ctx, _lib().bms_set_variant(ctx, int(kernel), int(variant)))
 
 
+def bms_get_variant(ctx, kernel):
+    v = ctypes.c_int()
+    _check(ctx, _lib().bms_get_variant(ctx, int(kernel), ctypes.byref(v)))
+    return v.value
+
+
+def bms_autotune(ctx, mass, n, shifts, precision, iters, B, X):
+    _check(ctx, _lib().bms_autotune(ctx, float(mass), int(n), len(shifts), _doubles(shifts),
+                                    int(precision), int(iters), _ptr(B), _ptr(X)))
+
+
+def bms_solve_batch(ctxs, masses, ns, shifts, tols, max_iters, opts, Bs, Xs, raise_on_error=True):
+    """Independent solves run concurrently, problem i on context ctxs[i].
+    Returns (status, [per-problem status], [per-problem stats dict])."""
+    k = len(ctxs)
+    vp = ctypes.c_void_p
+    sh = [_doubles(s) for s in shifts]
+    st = (bms_stats * k)()
+    res = [(ctypes.c_double * (len(shifts[i]) * ns[i]))() for i in range(k)]
+    for i in range(k):
+        st[i].true_residual = ctypes.cast(res[i], ctypes.POINTER(ctypes.c_double))
+    op = (bms_opts * k)()
+    for i in range(k):
+        op[i] = opts[i] if opts is not None else bms_default_opts()
+    status = (ctypes.c_int * k)()
+    rc = _lib().bms_solve_batch(
+        k, (vp * k)(*[c.value for c in ctxs]), (ctypes.c_double * k)(*map(float, masses)),
+        (ctypes.c_int * k)(*ns), (ctypes.c_int * k)(*[len(s) for s in shifts]),
+        (ctypes.POINTER(ctypes.c_double) * k)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+                                                for a in sh]),
+        (ctypes.c_double * k)(*map(float, tols)), (ctypes.c_int * k)(*max_iters), op,
+        (vp * k)(*[_ptr(b).value for b in Bs]), (vp * k)(*[_ptr(x).value for x in Xs]), st, status)
+    stats = []
+    for i in range(k):
+        nsh, n = len(shifts[i]), ns[i]
+        stats.append(dict(iterations=st[i].iterations, refine_iterations=st[i].refine_iterations,
+                          reliable_updates=st[i].reliable_updates, converged=bool(st[i].converged),
+                          max_true_residual=st[i].max_true_residual, status=status[i],
+                          true_residual=[[res[i][s * n + j] for j in range(n)] for s in range(nsh)]))
+    if raise_on_error and rc != 0:
+        bad = next(i for i in range(k) if status[i] != 0)
+        _check(ctxs[bad], status[bad])
+    return rc, list(status), stats
+
+
 def bms_timing_read(ctx, kernel):
     """Returns (milliseconds, launches, algorithmic bytes) accumulated for a kernel class."""
     ms, nl, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
@@ -289,6 +341,19 @@ class Context:
     def set_variant(self, kernel, variant):
         bms_set_variant(self.h, kernel, variant)
 
+    def get_variant(self, kernel):
+        return bms_get_variant(self.h, kernel)
+
+    def autotune(self, mass, shifts, B, precision=BMS_PREC_F64, iters=16):
+        """Time the kernel variants on this problem and keep the fastest;
+        returns {kernel name: chosen variant}."""
+        import torch
+        n = self._block(B, torch.complex128)
+        X = torch.empty((len(shifts),) + tuple(B.shape), dtype=torch.complex128, device=B.device)
+        bms_autotune(self.h, mass, n, list(shifts), precision, iters, B, X)
+        return {KERNEL_NAMES[k]: self.get_variant(k)
+                for k in (BMS_KERNEL_HOP, BMS_KERNEL_GRAM, BMS_KERNEL_UPDATE)}
+
     def timing(self, enable=True):
         bms_timing_enable(self.h, enable)
 
@@ -304,3 +369,21 @@ class Context:
             out = torch.empty((4, self.vol, 8), dtype=torch.float64, device=X.device)
         bms_force(self.h, n, list(alpha), X, out, flags)
         return out
+
+
+def solve_batch(contexts, masses, shifts, Bs, tol=1e-10, max_iter=10000, opts=None,
+                raise_on_error=True):
+    """bms_solve_batch over Context objects: problem i solves
+    (A_i + shifts[i][s]) X = Bs[i] on contexts[i]; all run concurrently.
+    Returns ([X_i], [stats_i])."""
+    import torch
+    k = len(contexts)
+    ns = [c._block(B, torch.complex128) for c, B in zip(contexts, Bs)]
+    Xs = [torch.empty((len(shifts[i]),) + tuple(Bs[i].shape), dtype=torch.complex128,
+                      device=Bs[i].device) for i in range(k)]
+    tols = tol if isinstance(tol, (list, tuple)) else [tol] * k
+    mits = max_iter if isinstance(max_iter, (list, tuple)) else [max_iter] * k
+    ops = opts if (opts is None or isinstance(opts, (list, tuple))) else [opts] * k
+    _, _, stats = bms_solve_batch([c.h for c in contexts], masses, ns, shifts, tols, mits, ops, Bs,
+                                  Xs, raise_on_error=raise_on_error)
+    return Xs, stats

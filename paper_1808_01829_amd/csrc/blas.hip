@@ -6,6 +6,8 @@
 // contiguous, right-hand side fastest. Threads map to (row, column) so that a
 // work-group's loads of a run of rows are one contiguous, coalesced span; the
 // row mixing of "block times n x n matrix" goes through LDS.
+#include <algorithm>
+
 #include "blas.h"
 
 namespace {
@@ -377,6 +379,25 @@ int gram_blocks(int rows, int n, int num_cu) {
 }
 
 static int rows_per_block(int rows, int nb) { return (rows + nb - 1) / nb; }
+
+namespace {
+__global__ __launch_bounds__(BMS_WG) void k_copy_if(uint4* __restrict__ dst,
+                                                    const uint4* __restrict__ src, size_t n16,
+                                                    const int* __restrict__ run_if) {
+  if (!*run_if) return;
+  for (size_t i = (size_t)blockIdx.x * BMS_WG + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * BMS_WG)
+    dst[i] = src[i];
+}
+}  // namespace
+
+hipError_t launch_copy_if(hipStream_t st, void* dst, const void* src, size_t bytes,
+                          const int* run_if) {
+  size_t n16 = bytes / 16;
+  unsigned blocks = (unsigned)std::min<size_t>((n16 + BMS_WG - 1) / BMS_WG, 8192);
+  if (n16) k_copy_if<<<blocks, BMS_WG, 0, st>>>((uint4*)dst, (const uint4*)src, n16, run_if);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_zero(hipStream_t st, void* p, size_t bytes) {
   size_t n16 = bytes / 16;

@@ -21,6 +21,7 @@ struct SolverFlags {
   int iter;       // completed block iterations
   int need_explicit;  // V^H V must come from the explicit Gram this iteration
   int rel_skip;       // the last reliable update kept the iterated residual
+  int rel_restart;    // one shift: the last reliable update restarts P^(0) = Q
   int active[BMS_MAX_SHIFTS];  // shift still updated
   int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
   double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift
@@ -98,3 +99,6 @@ hipError_t launch_block_matmul(hipStream_t st, int rows, int n, const void* X, c
                                void* Y);
 
 hipError_t launch_fill_zero(hipStream_t st, void* p, size_t bytes);
+// dst = src (bytes a multiple of 16) when *run_if is non-zero
+hipError_t launch_copy_if(hipStream_t st, void* dst, const void* src, size_t bytes,
+                          const int* run_if);

@@ -187,6 +187,7 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
   if (pass == 0 && threadIdx.x == 0) {
     fl->stop = 0;
     fl->halted = 0;
+    fl->rel_restart = 0;
     fl->error = 0;
     fl->iter = 0;
     fl->need_explicit = 0;
@@ -241,21 +242,53 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
   __shared__ double2 L0[NN], L1[NN], L2[NN];
   const int n = p.n;
   if (fl->stop) {
-    if (threadIdx.x == 0) fl->rel_skip = 1;
+    if (threadIdx.x == 0) {
+      fl->rel_skip = 1;
+      fl->rel_restart = 0;
+    }
     return;
   }
   sm_load(L0, Gin, n);
   int st = sm_chol_upper(L1, L0, n, p.breakdown_tol);
   if (st) {
     // columns of the true residual too unequal to factor: keep the iterated one
-    if (threadIdx.x == 0) fl->rel_skip = 1;
+    if (threadIdx.x == 0) {
+      fl->rel_skip = 1;
+      fl->rel_restart = 0;
+    }
     if (st == BMS_ENAN) raise_error(fl, st);
     return;
   }
+  // How far the true residual is from the iterated one (column norms of the
+  // new and the old delta). A large jump (the iterated residual had run far
+  // below the rounding drift, e.g. past Krylov exhaustion) leaves P^(0)
+  // inconsistent with the new Q: with one shift the search restarts from
+  // P^(0) = Q; with several the multi-shift iteration stops here and the
+  // per-shift defect correction takes over.
+  __shared__ double jump;
+  if (threadIdx.x == 0) {
+    double m = 0;
+    for (int i = 0; i < n; ++i) {
+      double ct = 0, ci = 0;
+      for (int k = 0; k < n; ++k) {
+        ct += cabs2(L1[k * n + i]);
+        ci += cabs2(s.delta[k * n + i]);
+      }
+      double r = sqrt(ct) / fmax(sqrt(ci), 1e-300);
+      m = r > m ? r : m;
+    }
+    jump = m;
+  }
+  __syncthreads();
   sm_triinv_upper(L2, L1, n);
   sm_store(Rinv_out, L2, n);
   sm_store(s.delta, L1, n);
-  if (threadIdx.x == 0) fl->rel_skip = 0;
+  if (threadIdx.x == 0) {
+    fl->rel_skip = 0;
+    const bool big = jump > 10.0;
+    fl->rel_restart = big && p.ns == 1;
+    if (big && p.ns > 1) fl->stop = 1;
+  }
 }
 
 // Completion of one iteration's small step: count this block's arrival and

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "blas.h"
@@ -54,6 +55,7 @@ enum Slot {
 };
 
 const double kEps = 2.220446049250313e-16;
+const double kEps32 = 1.1920928955078125e-07;
 const size_t kFlagsBytes = sizeof(SolverFlags) + 4 * CNT_STRIDE * sizeof(int) + 64;
 
 // partial sums of a grid reduction over nb blocks of P entries, plus the
@@ -230,6 +232,8 @@ int enqueue_reliable(bms_ctx* c, const Work& w, const SmallParams& sp, double ma
   HIP_TRY(c, launch_small_reliable(c->stream, sp, w.sm, w.flags, w.Gtmp, w.Rinv));
   HIP_TRY(c, launch_block_matmul_d<float>(c->stream, w.rows, w.n, R0, w.Rinv, w.Q,
                                           &w.flags->rel_skip));
+  // one shift and a large jump: the search direction restarts from the new Q
+  HIP_TRY(c, launch_copy_if(c->stream, w.P, w.Q, w.blk * sizeof(float2), &w.flags->rel_restart));
   return BMS_OK;
 }
 
@@ -239,6 +243,78 @@ struct CoreResult {
   int soft = 0;   // the iteration stopped early on breakdown / non-finite values
   int reliable = 0;
 };
+
+// Everything the kernels of one iteration receive by value or address: a
+// captured chunk of iterations can be replayed while this is unchanged.
+template <typename T>
+std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, double mass, int K) {
+  struct {
+    const void* p[16];
+    double mass;
+    int K, n, ns, nb, hop_v, gram_v, upd_v, prec;
+    SmallParams sp;
+    SmallState sm;
+  } k;
+  memset(&k, 0, sizeof k);
+  const void* ptrs[16] = {w.W1, w.W, w.Q, w.P, w.X, w.Mx, w.Mp, w.flags, w.partials, w.counters,
+                          c->links64.p, c->links32.p, nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < 16; ++i) k.p[i] = ptrs[i];
+  k.mass = mass;
+  k.K = K;
+  k.n = w.n;
+  k.ns = w.ns;
+  k.nb = w.nb;
+  k.hop_v = c->hop_variant;
+  k.gram_v = c->gram_variant;
+  k.upd_v = c->update_variant;
+  k.prec = (int)sizeof(T);
+  k.sp = sp;
+  k.sm = w.sm;
+  return std::string((const char*)&k, sizeof k);
+}
+
+// Enqueue K iterations: replayed from a captured hipGraph when allowed (the
+// chunk holds kernel launches only), else launched directly (with per-kernel
+// events when timing).
+template <typename T>
+int enqueue_chunk(bms_ctx* c, const Work& w, const SmallParams& sp, double mass, int K,
+                  bool use_graph) {
+  if (!use_graph || c->timing) {
+    for (int k = 0; k < K; ++k) {
+      int rc = enqueue_iteration<T>(c, w, sp, mass, c->timing ? &c->evpool[8 * k] : nullptr);
+      if (rc) return rc;
+    }
+    return BMS_OK;
+  }
+  std::string key = chunk_key<T>(c, w, sp, mass, K);
+  if (!c->graph_exec || c->graph_key != key) {
+    if (c->graph_exec) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));  // an earlier replay may still run
+      HIP_TRY(c, hipGraphExecDestroy(c->graph_exec));
+      c->graph_exec = nullptr;
+    }
+    c->graph_key.clear();
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = BMS_OK;
+    for (int k = 0; k < K && rc == BMS_OK; ++k) rc = enqueue_iteration<T>(c, w, sp, mass, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return set_err(c, BMS_EHIP, "stream capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->graph_exec = nullptr;
+      return set_err(c, BMS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    c->graph_key = key;
+  }
+  HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+  return BMS_OK;
+}
 
 // One block multi-shift solve from X = 0. sigma[] ascending; the solution of
 // sigma[s] is written to Xout + xmap[s] * blk (FP64), which must not alias B.
@@ -258,8 +334,9 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
   sp.tol = 0.5 * tol;
   double ft = o.freeze_tol > 0 ? o.freeze_tol : sp.tol;
   sp.freeze_tol = ft < sp.tol ? ft : sp.tol;
-  // a computed Gram resolves pivots only down to ~eps * trace
-  sp.breakdown_tol = 10.0 * n * kEps;
+  // a computed Gram resolves pivots only down to ~eps * trace, eps of the
+  // block vectors' precision (FP32 blocks in the mixed solver)
+  sp.breakdown_tol = 10.0 * n * (mixed ? kEps32 : kEps);
   for (int s = 0; s < ns; ++s) sp.sigma[s] = sigma[s];
   Work w;
   if ((rc = alloc_work<T>(c, n, ns, max_iter, w))) return rc;
@@ -283,9 +360,7 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
     for (size_t i = old; i < c->evpool.size(); ++i) HIP_TRY(c, hipEventCreate(&c->evpool[i]));
   }
   while (true) {
-    for (int k = 0; k < K; ++k)
-      if ((rc = enqueue_iteration<T>(c, w, sp, mass, c->timing ? &c->evpool[8 * k] : nullptr)))
-        return rc;
+    if ((rc = enqueue_chunk<T>(c, w, sp, mass, K, o.use_graph != 0))) return rc;
     if (mixed && enqueued + K - last_rel >= o.reliable_interval) {
       if ((rc = enqueue_reliable(c, w, sp, mass, B, Xout, xmap, R1, R2, R0, false))) return rc;
       last_rel = enqueued + K;

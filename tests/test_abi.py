@@ -122,3 +122,44 @@ def test_null_context(lib):
     assert lib.bms_destroy(None) == bms.BMS_EINVAL
     assert lib.bms_set_gauge(None, None) == bms.BMS_EINVAL
     assert lib.bms_last_error(None) == b""
+
+
+def test_driver_entry_points_reject_bad_calls(lib):
+    rc, ctx = _create(lib, (4, 4, 4, 4))
+    rc2, ctx2 = _create(lib, (2, 2, 2, 2))
+    assert rc == bms.BMS_OK and rc2 == bms.BMS_OK
+    try:
+        v = ctypes.c_int(-5)
+        assert lib.bms_get_variant(ctx, bms.BMS_KERNEL_UPDATE, ctypes.byref(v)) == bms.BMS_OK
+        assert v.value == -1
+        assert lib.bms_get_variant(ctx, bms.BMS_KERNEL_SMALL, ctypes.byref(v)) == bms.BMS_EINVAL
+        assert lib.bms_get_variant(None, 0, ctypes.byref(v)) == bms.BMS_EINVAL
+        sh = (ctypes.c_double * 2)(0.1, 0.2)
+        dummy, other = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+        assert lib.bms_autotune(ctx, 0.1, 1, 2, sh, bms.BMS_PREC_F32, 8, dummy, other) == bms.BMS_EINVAL
+        assert lib.bms_autotune(ctx, 0.1, 1, 2, sh, bms.BMS_PREC_F64, 0, dummy, other) == bms.BMS_EINVAL
+        # well-formed but no gauge field: the solve it runs fails on the host
+        assert lib.bms_autotune(ctx, 0.1, 1, 2, sh, bms.BMS_PREC_F64, 8, dummy, other) == bms.BMS_ESTATE
+        # batch: argument checks, then per-problem status
+        k = 2
+        vp = ctypes.c_void_p
+        ctxs = (vp * k)(ctx.value, ctx2.value)
+        mass = (ctypes.c_double * k)(0.1, 0.1)
+        n = (ctypes.c_int * k)(1, 1)
+        nsh = (ctypes.c_int * k)(2, 2)
+        shp = (ctypes.POINTER(ctypes.c_double) * k)(ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)),
+                                                     ctypes.cast(sh, ctypes.POINTER(ctypes.c_double)))
+        tol = (ctypes.c_double * k)(1e-8, 1e-8)
+        mi = (ctypes.c_int * k)(100, 100)
+        Bp = (vp * k)(0x1000, 0x3000)
+        Xp = (vp * k)(0x2000, 0x4000)
+        status = (ctypes.c_int * k)(7, 7)
+        args = [mass, n, nsh, shp, tol, mi, None, Bp, Xp, None, status]
+        assert lib.bms_solve_batch(0, ctxs, *args) == bms.BMS_EINVAL
+        same = (vp * k)(ctx.value, ctx.value)
+        assert lib.bms_solve_batch(k, same, *args) == bms.BMS_EINVAL
+        assert lib.bms_solve_batch(k, ctxs, *args) == bms.BMS_ESTATE
+        assert list(status) == [bms.BMS_ESTATE, bms.BMS_ESTATE]
+    finally:
+        assert lib.bms_destroy(ctx) == bms.BMS_OK
+        assert lib.bms_destroy(ctx2) == bms.BMS_OK

@@ -1,0 +1,87 @@
+"""hipGraph replay, autotuning and the batch of independent solves."""
+import numpy as np
+import pytest
+
+from gpu_common import to_dev, to_np, torch_gpu
+from oracle import oracle as O
+from paper_1808_01829_amd.inputs import configs, gaussian_block, random_gauge
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_gpu()
+
+
+def _problem(torch, dims, n, seed, eps=0.5):
+    from paper_1808_01829_amd import bms
+    U = random_gauge(dims, eps, seed)
+    B = gaussian_block(dims, n, seed + 1)
+    ctx = bms.Context(dims, BC)
+    ctx.set_gauge(to_dev(torch, U))
+    return ctx, U, B
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_graph_replay_matches_direct_launches(torch, prec):
+    """Chunks replayed from the captured graph give the same iterates as direct
+    launches, bit for bit, over several solves in a row (re-captured when the
+    solve changes), with eager work and synchronisation in between."""
+    from paper_1808_01829_amd import bms
+    p = bms.BMS_PREC_F64 if prec == "f64" else bms.BMS_PREC_MIXED
+    r = configs.workload_coefficients("c2")
+    ctx, U, B = _problem(torch, (4, 4, 4, 6), 8, 41)
+    Bd = to_dev(torch, B)
+    runs = [(r.beta, 1e-10, 300), (r.beta[:5], 1e-8, 37), (r.beta, 1e-10, 300)]
+    for shifts, tol, mi in runs:
+        res = {}
+        for g in (0, 1, 1, 0, 1):
+            X, st = ctx.solve(0.05, shifts, Bd, tol=tol, max_iter=mi, precision=p, use_graph=g,
+                              raise_on_error=False)
+            torch.cuda.synchronize()
+            _ = (Bd * 2).sum().item()  # eager work between replays
+            res.setdefault(g, []).append((to_np(X), st["iterations"]))
+        ref, it = res[0][0]
+        for g, lst in res.items():
+            for X, its in lst:
+                assert its == it
+                assert np.array_equal(X, ref), (g, tol)
+
+
+def test_autotune_keeps_solves_correct(torch):
+    from paper_1808_01829_amd import bms
+    r = configs.workload_coefficients("c2")
+    ctx, U, B = _problem(torch, (6, 4, 4, 6), 16, 51)
+    Bd = to_dev(torch, B)
+    for prec in (bms.BMS_PREC_F64, bms.BMS_PREC_MIXED):
+        chosen = ctx.autotune(0.05, r.beta, Bd, precision=prec, iters=8)
+        assert chosen["hop"] in (0, 1) and chosen["gram"] in (0, 2, 3)
+        assert chosen["update"] in (0, 2, 4, 5)
+        X, st = ctx.solve(0.05, r.beta, Bd, tol=1e-10, precision=prec)
+        tr = O.true_residuals((6, 4, 4, 6), BC, U, 0.05, r.beta, B, to_np(X))
+        assert tr.max() <= 1e-10
+
+
+def test_uneven_batch_equals_individual_solves(torch):
+    """An uneven batch (three lattices, three widths) solved concurrently gives
+    the same solutions as solving each alone."""
+    from paper_1808_01829_amd import bms
+    r = configs.workload_coefficients("c2")
+    probs = [((4, 4, 4, 4), 4, 61), ((6, 6, 6, 6), 16, 63), ((8, 8, 8, 8), 8, 65)]
+    ctxs, Us, Bs = [], [], []
+    for dims, n, seed in probs:
+        c, U, B = _problem(torch, dims, n, seed)
+        ctxs.append(c)
+        Us.append(U)
+        Bs.append(to_dev(torch, B))
+    shifts = [r.beta, r.beta[2:], r.beta]
+    Xs, stats = bms.solve_batch(ctxs, [0.05] * 3, shifts, Bs, tol=1e-10)
+    for i, (dims, n, seed) in enumerate(probs):
+        assert stats[i]["status"] == 0 and stats[i]["converged"]
+        X1, st1 = ctxs[i].solve(0.05, shifts[i], Bs[i], tol=1e-10)
+        assert st1["iterations"] == stats[i]["iterations"]
+        assert np.array_equal(to_np(X1), to_np(Xs[i]))
+        tr = O.true_residuals(dims, BC, Us[i], 0.05, shifts[i], to_np(Bs[i]), to_np(Xs[i]))
+        assert tr.max() <= 1e-10
