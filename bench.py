@@ -13,6 +13,9 @@ time, inputs resident in HBM. Printed as one JSON line, with:
                 the kernel's source changed since the counters were taken
   per_vector    the same library at n = 1 in FP64 (multi-shift CG per column)
   other_precision  the same solve in the other precision (FP64 <-> mixed)
+  autotuned     kernel variants bms_autotune picked on this problem (before warmup)
+  batch         the workload's uneven batch of lattices through bms_solve_batch
+                (all at once) and one after the other
   cpu_baseline  the FP64 CPU oracle's multi-shift CG on a bounded sample
 The precision of the timed solves is the workload's (mixed at 32^4).
 """
@@ -88,6 +91,42 @@ def stored_traffic(workload, prec, kernel):
     return k.get("bytes_per_launch")
 
 
+def run_batch(args, w, r, bms, opts, torch, np):
+    """The workload's uneven batch (same mass, disorder, n_pf and poles on each
+    lattice): one bms_solve_batch (all concurrently), then the same solves one
+    after the other; RHS columns with every shift at tol, per second."""
+    from paper_1808_01829_amd.inputs import gaussian_block, random_gauge
+    ctxs, Bs = [], []
+    for k, dims in enumerate(w["batch"]):
+        U = random_gauge(dims, w["eps"], 1000 * w["id"] + 10 * (k + 1))
+        B = gaussian_block(dims, w["n"], 1000 * w["id"] + 10 * (k + 1) + 1)
+        c = bms.Context(dims, (1, 1, 1, -1))
+        c.set_gauge(torch.from_numpy(U).to("cuda:0"))
+        ctxs.append(c)
+        Bs.append(torch.from_numpy(B).to("cuda:0"))
+    k = len(ctxs)
+    shifts = [r.beta] * k
+    ops = [opts] * k
+    bms.solve_batch(ctxs, [w["mass"]] * k, shifts, Bs, tol=w["tol"], max_iter=20000, opts=ops)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stats = bms.solve_batch(ctxs, [w["mass"]] * k, shifts, Bs, tol=w["tol"], max_iter=20000,
+                               opts=ops, raise_on_error=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    solved = sum(int(np.sum(np.all(np.asarray(st["true_residual"]) <= w["tol"], axis=0)))
+                 for st in stats)
+    t0 = time.perf_counter()
+    for c, B in zip(ctxs, Bs):
+        c.solve(w["mass"], r.beta, B, tol=w["tol"], max_iter=20000, opts=opts)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return dict(lattices=["x".join(map(str, d)) for d in w["batch"]], n_pf=w["n"],
+                value=round(solved / tb, 4), unit="RHS-solves/s", s_concurrent=round(tb, 3),
+                s_sequential=round(ts, 3), iterations=[st["iterations"] for st in stats],
+                max_true_residual=max(st["max_true_residual"] for st in stats))
+
+
 def per_vector(ctx, bms, m, r, Bd, tol, cols, torch):
     """Same library, n = 1, FP64, one column at a time (multi-shift CG)."""
     iters = []
@@ -115,6 +154,10 @@ def main():
     ap.add_argument("--other-precision", type=int, default=1,
                     help="also time this many solves in the other precision (reported aside)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip bms_autotune (kernel variants picked on this problem before warmup)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the workload's uneven batch of lattices (reported aside)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -147,6 +190,11 @@ def main():
     if w.get("reliable"):
         opts.reliable_interval = w["reliable"]
 
+    tuned = None
+    if not args.no_autotune:
+        t = time.time()
+        tuned = ctx.autotune(m, r.beta, Bd, precision=opts.precision, iters=16)
+        log("bench: autotune %.1f s: %s" % (time.time() - t, tuned))
     X = None
     for i in range(args.warmup):
         X, st = ctx.solve(m, r.beta, Bd, tol=tol, max_iter=20000, opts=opts)
@@ -217,6 +265,11 @@ def main():
                      max_true_residual=ost["max_true_residual"])
         log("bench: %s: %s" % (op, other))
 
+    batch = None
+    if w.get("batch") and not args.no_batch:
+        batch = run_batch(args, w, r, bms, opts, torch, np)
+        log("bench: batch %s" % (batch,))
+
     cpu = None
     if not args.no_cpu:
         try:
@@ -242,6 +295,8 @@ def main():
                         iterations=pv_iters, dtype="f64"),
         block_over_per_vector=round(value / pv_rate, 3) if pv_rate == pv_rate else None,
         other_precision=other,
+        autotuned=tuned,
+        batch=batch,
         iterations=iters, max_true_residual=maxres,
         dslash_gbs=kernels.get("hop", {}).get("gbs"),
         kernels=kernels,

@@ -73,6 +73,7 @@ struct SmallState {
   double2* G4;      // [4][n*n]  P^H W, Q^H W, W^H W, Q^H Q of the iteration
   double2* Gqr;     // [n*n]     output of the V^H V Gram
   double2* tmp;     // [n*n]     scratch
+  double* rel_last; // smallest max relative true residual of sigma_0 at a reliable update
   int* counter;     // grid-completion counter of the rho kernel
   int* nact_log;    // [max_iter] active shifts in each completed iteration
 };

@@ -804,7 +804,108 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
 // GCH rows of P, Q and W (coalesced, the next chunk prefetched into registers
 // while the current one is reduced) and each wave owns one product:
 // wave 0 P^H W, 1 Q^H W, 2 W^H W, 3 Q^H Q, so a wave holds at most four tiles.
+// Per chunk a wave reads all its operands from LDS before its MFMAs; the
+// symmetric and the general products run separate loops.
 constexpr int GCH = 32;
+
+template <typename T, int N>
+struct GramStage {
+  using C_ = cplx<T>;
+  static constexpr int RS = N + 1;                 // staged row stride (complex), padded
+  static constexpr int BS = GCH * RS;              // one staged block
+  static constexpr int PER_T = GCH * N / BMS_WG;   // complex per thread and block
+};
+
+// operands of row rl of a staged block (GramRow's tile mapping)
+template <typename T, int N>
+__device__ __forceinline__ void gram_operand(const cplx<T>* blk, int rl, int c,
+                                             double (&v)[GramRow<T, N>::NT]) {
+  using C_ = cplx<T>;
+  constexpr int RS = GramStage<T, N>::RS;
+  if constexpr (N == 16) {
+    C_ z = blk[rl * RS + c];
+    v[0] = (double)z.x;
+    v[1] = (double)z.y;
+  } else {
+    v[0] = (double)((const decltype(C_().x)*)(blk + rl * RS))[c];
+  }
+}
+
+// one chunk of one wave's product: all GCH/4 steps' operands, then the MFMAs
+template <typename T, int N, bool SYM>
+__device__ __forceinline__ void gram_chunk(const cplx<T>* xs, const cplx<T>* ys, int g, int c,
+                                           gdx4 (&acc)[GramRow<T, N>::NT][GramRow<T, N>::NT]) {
+  constexpr int NT = GramRow<T, N>::NT, ST = GCH / 4;
+  double x[ST][NT], y[ST][NT];
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    gram_operand<T, N>(xs, 4 * st + g, c, x[st]);
+    if constexpr (!SYM) gram_operand<T, N>(ys, 4 * st + g, c, y[st]);
+  }
+#pragma unroll
+  for (int st = 0; st < ST; ++st)
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = SYM ? a : 0; b < NT; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[st][a], SYM ? x[st][b] : y[st][b],
+                                                         acc[a][b], 0, 0, 0);
+}
+
+template <typename T, int N, bool SYM>
+__device__ __forceinline__ void gram_sweep(const cplx<T>* P, const cplx<T>* Q, const cplx<T>* W,
+                                           RowRange rr, cplx<T>* stage, int xb, int yb,
+                                           gdx4 (&acc)[GramRow<T, N>::NT][GramRow<T, N>::NT]) {
+  using C_ = cplx<T>;
+  using GS = GramStage<T, N>;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const C_* src[3] = {P, Q, W};
+  C_ nx[3][GS::PER_T];
+  // chunk loader: element e = tid + k*256 of the chunk's rows x N complex; a
+  // full chunk loads without conditions, only a ragged last one checks rows
+  auto fetch = [&](int r0) {
+    if (r0 + GCH <= rr.r1) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int k = 0; k < GS::PER_T; ++k) nx[b][k] = src[b][(size_t)r0 * N + tid + k * BMS_WG];
+    } else {
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int k = 0; k < GS::PER_T; ++k) {
+          int e = tid + k * BMS_WG;
+          bool ok = r0 + e / N < rr.r1;
+          nx[b][k] = ok ? src[b][(size_t)r0 * N + e] : czero<C_>();
+        }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int k = 0; k < GS::PER_T; ++k) {
+        int e = tid + k * BMS_WG;
+        stage[(buf * 3 + b) * GS::BS + (e / N) * GS::RS + (e % N)] = nx[b][k];
+      }
+  };
+  int buf = 0;
+  if (rr.r0 < rr.r1) {
+    fetch(rr.r0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int r0 = rr.r0; r0 < rr.r1; r0 += GCH) {
+    const bool more = r0 + GCH < rr.r1;
+    if (more) fetch(r0 + GCH);
+    gram_chunk<T, N, SYM>(stage + (buf * 3 + xb) * GS::BS, stage + (buf * 3 + yb) * GS::BS, g, c,
+                          acc);
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
 
 template <typename T, int N>
 __global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
@@ -817,12 +918,10 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
                                                       const int* __restrict__ skip) {
   using C_ = cplx<T>;
   using GR = GramRow<T, N>;
+  using GS = GramStage<T, N>;
   constexpr int NR = 2 * N, NT = GR::NT, NN = N * N;
-  constexpr int RS = N + 1;            // staged row stride (complex), padded
-  constexpr int BS = GCH * RS;         // one staged block
-  constexpr int PER_T = GCH * N / BMS_WG;  // complex per thread and block
-  static_assert(PER_T >= 1 && GCH * N % BMS_WG == 0, "chunk must cover the block");
-  constexpr int STAGE = 2 * 3 * BS * (int)sizeof(C_);
+  static_assert(GS::PER_T >= 1 && GCH * N % BMS_WG == 0, "chunk must cover the block");
+  constexpr int STAGE = 2 * 3 * GS::BS * (int)sizeof(C_);
   constexpr int REDB = 4 * NR * NR * (int)sizeof(double);
   __shared__ __align__(16) unsigned char smem[STAGE > REDB ? STAGE : REDB];
   if (skip && *skip) return;
@@ -830,7 +929,6 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
   const RowRange rr = block_rows(rows, per_block);
-  const C_* src[3] = {P, Q, W};
   // this wave's product: x block and y block (0 = P, 1 = Q, 2 = W)
   const int xb = wave == 0 ? 0 : (wave == 2 ? 2 : 1);
   const int yb = wave == 3 ? 1 : 2;
@@ -840,71 +938,10 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
   for (int a = 0; a < NT; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = gdx4{0.0, 0.0, 0.0, 0.0};
-  // chunk loader: element e = tid + k*256 of the chunk's rows x N complex
-  C_ nx[3][PER_T];
-  auto fetch = [&](int r0) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int k = 0; k < PER_T; ++k) {
-        int e = tid + k * BMS_WG;
-        int r = r0 + e / N;
-        bool ok = r < rr.r1;
-        C_ z = src[b][(size_t)(ok ? r : 0) * N + (e % N)];
-        nx[b][k] = ok ? z : czero<C_>();
-      }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int k = 0; k < PER_T; ++k) {
-        int e = tid + k * BMS_WG;
-        stage[(buf * 3 + b) * BS + (e / N) * RS + (e % N)] = nx[b][k];
-      }
-  };
-  // operands of row rl of a staged block (see GramRow for the tile mapping)
-  auto operand = [&](const C_* blk, int rl, double (&v)[NT]) {
-    if constexpr (N == 16) {
-      C_ z = blk[rl * RS + c];
-      v[0] = (double)z.x;
-      v[1] = (double)z.y;
-    } else {
-      v[0] = (double)((const decltype(C_().x)*)(blk + rl * RS))[c];
-    }
-  };
-  int buf = 0;
-  if (rr.r0 < rr.r1) {
-    fetch(rr.r0);
-    stash(0);
-  }
-  __syncthreads();
-  for (int r0 = rr.r0; r0 < rr.r1; r0 += GCH) {
-    const bool more = r0 + GCH < rr.r1;
-    if (more) fetch(r0 + GCH);
-    const C_* xs = stage + (buf * 3 + xb) * BS;
-    const C_* ys = stage + (buf * 3 + yb) * BS;
-#pragma unroll 2
-    for (int st = 0; st < GCH / 4; ++st) {
-      double x[NT], y[NT];
-      operand(xs, 4 * st + g, x);
-      if (sym) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) y[t] = x[t];
-      } else {
-        operand(ys, 4 * st + g, y);
-      }
-#pragma unroll
-      for (int a = 0; a < NT; ++a)
-#pragma unroll
-        for (int b = 0; b < NT; ++b)
-          if (!sym || b >= a)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[b], acc[a][b], 0, 0, 0);
-    }
-    if (more) stash(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
+  if (sym)
+    gram_sweep<T, N, true>(P, Q, W, rr, stage, xb, yb, acc);
+  else
+    gram_sweep<T, N, false>(P, Q, W, rr, stage, xb, yb, acc);
   // each wave's real Gram into LDS (tile row g + 4k, column c), then the
   // complex entries of all four products
   double* R = (double*)smem + wave * NR * NR;

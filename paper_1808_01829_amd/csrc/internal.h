@@ -22,6 +22,8 @@ struct SolverFlags {
   int need_explicit;  // V^H V must come from the explicit Gram this iteration
   int rel_skip;       // the last reliable update kept the iterated residual
   int rel_restart;    // one shift: the last reliable update restarts P^(0) = Q
+  int diverged;       // the true residual grew or stalled over reliable updates (soft stop)
+  int rel_stall;      // reliable updates in a row without progress of the true residual
   int active[BMS_MAX_SHIFTS];  // shift still updated
   int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
   double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift

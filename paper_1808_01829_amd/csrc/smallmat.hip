@@ -188,6 +188,9 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
     fl->stop = 0;
     fl->halted = 0;
     fl->rel_restart = 0;
+    fl->diverged = 0;
+    fl->rel_stall = 0;
+    *s.rel_last = 1e300;
     fl->error = 0;
     fl->iter = 0;
     fl->need_explicit = 0;
@@ -265,9 +268,14 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
   // inconsistent with the new Q: with one shift the search restarts from
   // P^(0) = Q; with several the multi-shift iteration stops here and the
   // per-shift defect correction takes over.
-  __shared__ double jump;
+  // It also watches the true residual itself: growth beyond 2x its smallest
+  // value so far, or four reliable updates in a row without a 1% gain, means
+  // the FP32 iteration diverges or stalls (e.g. after Krylov exhaustion on a
+  // small lattice); the loop then stops softly and the caller falls back to
+  // FP64.
+  __shared__ double jump, trel;
   if (threadIdx.x == 0) {
-    double m = 0;
+    double m = 0, mt = 0;
     for (int i = 0; i < n; ++i) {
       double ct = 0, ci = 0;
       for (int k = 0; k < n; ++k) {
@@ -276,8 +284,11 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
       }
       double r = sqrt(ct) / fmax(sqrt(ci), 1e-300);
       m = r > m ? r : m;
+      double t = sqrt(ct) / s.norm0[i];
+      mt = t > mt ? t : mt;
     }
     jump = m;
+    trel = mt;
   }
   __syncthreads();
   sm_triinv_upper(L2, L1, n);
@@ -288,6 +299,17 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
     const bool big = jump > 10.0;
     fl->rel_restart = big && p.ns == 1;
     if (big && p.ns > 1) fl->stop = 1;
+    const double best = *s.rel_last;
+    if (trel < 0.99 * best) {
+      *s.rel_last = trel;
+      fl->rel_stall = 0;
+    } else {
+      fl->rel_stall += 1;
+    }
+    if (!(trel <= 2.0 * best) || fl->rel_stall >= 4) {
+      fl->diverged = 1;
+      fl->stop = 1;
+    }
   }
 }
 

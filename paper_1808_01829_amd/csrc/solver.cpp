@@ -91,7 +91,7 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   if ((rc = scratch_buf(c, S_P, w.blk * es * ns, &w.P))) return rc;
   if ((rc = scratch_buf(c, S_X, w.blk * es * ns, &w.X))) return rc;
   size_t nn = (size_t)n * n;
-  size_t small_elems = 2 * nn + 2 * nn + 8 * nn + 2 * ns * nn + 3 * nn + n;
+  size_t small_elems = 2 * nn + 2 * nn + 8 * nn + 2 * ns * nn + 3 * nn + n + 1;
   void* sp;
   if ((rc = scratch_buf(c, S_SMALL, small_elems * sizeof(double2) + 64, &sp))) return rc;
   double2* d = (double2*)sp;
@@ -120,6 +120,7 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   w.Gtmp = d;
   d += nn;
   w.sm.norm0 = (double*)d;
+  w.sm.rel_last = (double*)d + n;
   w.nb = gram_blocks(w.rows, n, c->num_cu);
   void* pp;
   if ((rc = scratch_buf(c, S_PART, part_bytes(w.nb, 4 * nn), &pp))) return rc;
@@ -242,6 +243,7 @@ struct CoreResult {
   int error = 0;  // final failure (initial QR)
   int soft = 0;   // the iteration stopped early on breakdown / non-finite values
   int reliable = 0;
+  bool diverged = false;  // the mixed iteration's true residual grew (stopped softly)
 };
 
 // Everything the kernels of one iteration receive by value or address: a
@@ -408,6 +410,7 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
                                 c->stream));
   }
   cr.iters = hf.iter;
+  cr.diverged = hf.diverged != 0;
   // A breakdown or non-finite value inside the iteration stops it with the
   // last finite iterate in X (the update of that step is skipped); the true
   // residual check and defect correction then decide. Only a failure of the
@@ -500,16 +503,36 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
   if ((rc = solve_core<T>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X, cr)))
     return rc;
   int refine_iters = 0, reliable = cr.reliable;
+  bool fell_back = false;
+  if (sizeof(T) == 4 && cr.diverged) {
+    // the FP32 iteration diverged or stalled: solve all shifts again in FP64
+    // (one multi-shift solve is cheaper than refining every shift on its own)
+    refine_iters += cr.iters;
+    CoreResult c64;
+    if ((rc = solve_core<double>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X,
+                                 c64)))
+      return rc;
+    cr = c64;
+    cr.reliable = reliable;
+    fell_back = true;
+  }
   std::vector<double> rn2, bn2;
   if ((rc = residual_norms(c, mass, n, ns, shifts, B, X, rn2, bn2))) return rc;
-  // defect correction of the shifts that miss tol
+  // defect correction of the shifts that miss tol. In the mixed solver the
+  // corrections run in FP32 unless a shift's FP32 correction diverged or did
+  // not gain a factor 10, then in FP64; a shift whose residual is worse than
+  // that of X = 0 (a diverged main iteration) restarts from X = 0.
+  const bool mixed = sizeof(T) == 4;
+  std::vector<char> use64(ns, fell_back ? 1 : 0);
   int rows = 3 * c->vh;
   size_t blk = (size_t)rows * n;
   for (int round = 0; round < o.max_refine && !cr.error; ++round) {
     std::vector<int> bad;
+    std::vector<double> before(ns, 0.0);
     for (int s = 0; s < ns; ++s) {
       double m = 0;
       for (int i = 0; i < n; ++i) m = std::max(m, std::sqrt(rn2[s * n + i] / bn2[i]));
+      before[s] = m;
       if (!(m <= tol)) bad.push_back(s);
     }
     if (bad.empty()) break;
@@ -520,6 +543,11 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
     if ((rc = scratch_buf(c, S_R1, blk * sizeof(double2), &t1))) return rc;
     if ((rc = scratch_buf(c, S_R2, blk * sizeof(double2), &t2))) return rc;
     for (int s : bad) {
+      if (!(before[s] <= 1.0)) {
+        // worse than no solution at all (or not finite): start again from 0
+        HIP_TRY(c, launch_fill_zero(c->stream, (double2*)X + s * blk, blk * sizeof(double2)));
+        for (int i = 0; i < n; ++i) rn2[s * n + i] = bn2[i];
+      }
       // column-normalised residual R'_i = r_i / |r_i| (B's column if r_i = 0)
       std::vector<double> h(3 * n);
       double worst = 0;
@@ -529,10 +557,6 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
         h[n + i] = bn > 0 ? 1.0 / bn : 1.0;
         h[2 * n + i] = rn;
         worst = std::max(worst, rn / bn);
-      }
-      if (!std::isfinite(worst)) {
-        cr.error = BMS_ENAN;
-        break;
       }
       const double2* xs = (const double2*)X + s * blk;
       HIP_TRY(c, hipMemcpyAsync(cols, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -546,9 +570,18 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
       CoreResult ci;
       int zero = 0;
       double sg = shifts[s];
-      if ((rc = solve_core<T>(c, mass, n, 1, &sg, &zero, tin, max_iter, o, RB, E, ci))) return rc;
+      const bool in64 = !mixed || use64[s];
+      if (in64)
+        rc = solve_core<double>(c, mass, n, 1, &sg, &zero, tin, max_iter, o, RB, E, ci);
+      else
+        rc = solve_core<T>(c, mass, n, 1, &sg, &zero, tin, max_iter, o, RB, E, ci);
+      if (rc) return rc;
       refine_iters += ci.iters;
       reliable += ci.reliable;
+      if (ci.diverged) {
+        use64[s] = 1;  // E is not a usable correction; FP64 next round
+        continue;
+      }
       if (ci.error == BMS_EBREAKDOWN) {
         // the normalised residual columns are nearly dependent (typically a
         // few lowest modes left): refine them one column at a time
@@ -560,10 +593,17 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
           double ti = std::min(0.5, std::max(0.5 * tol * std::sqrt(bn2[i]) / h[2 * n + i], 1e-13));
           HIP_TRY(c, launch_gather_col(c->stream, rows, n, i, RB, bc));
           CoreResult cc;
-          if ((rc = solve_core<T>(c, mass, 1, 1, &sg, &zero, ti, max_iter, o, bc, ec, cc)))
-            return rc;
+          if (in64)
+            rc = solve_core<double>(c, mass, 1, 1, &sg, &zero, ti, max_iter, o, bc, ec, cc);
+          else
+            rc = solve_core<T>(c, mass, 1, 1, &sg, &zero, ti, max_iter, o, bc, ec, cc);
+          if (rc) return rc;
           refine_iters += cc.iters;
           reliable += cc.reliable;
+          if (cc.diverged) {
+            use64[s] = 1;
+            continue;
+          }
           if (cc.error) {
             cr.error = cc.error;
             break;
@@ -582,6 +622,12 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
                                   (const double*)cols + 2 * n));
     }
     if ((rc = residual_norms(c, mass, n, ns, shifts, B, X, rn2, bn2))) return rc;
+    if (mixed)
+      for (int s : bad) {
+        double m = 0;
+        for (int i = 0; i < n; ++i) m = std::max(m, std::sqrt(rn2[s * n + i] / bn2[i]));
+        if (!(m <= 0.1 * before[s]) && !(m <= tol)) use64[s] = 1;
+      }
   }
   double mx = 0;
   std::vector<double> res((size_t)ns * n);
