@@ -195,7 +195,7 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
  * work, and their algorithmic HBM bytes (each block vector, link and solution
  * read or written once per launch; small n x n data not counted):
  *   BMS_KERNEL_HOP      half hop, links + in + out (+ aux for the D_eo hop)
- *   BMS_KERNEL_GRAM     P^H W Gram: 2 blocks read
+ *   BMS_KERNEL_GRAM     the iteration's four Grams: P, Q, W read
  *   BMS_KERNEL_CHOLQR   Cholesky-QR Gram: Q, W read
  *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per active
  *                       shift P^(s), X^(s) read and written
@@ -213,15 +213,17 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
 int bms_timing_enable(bms_ctx* ctx, int enable);
 
 /*
- * Kernel variant selection. For BMS_KERNEL_UPDATE: 4 = the matrix-core
- * (MFMA) kernel, used for FP64 at n = 8 and 16; 0..3 = the vector kernels
- * at n = 8 and 16 (0 = four row chunks per work-group with both coefficient
- * columns in registers, 1 = two chunks, one column at a time, 2 = four
- * chunks, one column at a time, 3 = two chunks, both columns); -1 restores
- * the built-in default (4 where it applies, else 2). For BMS_KERNEL_GRAM:
- * 1 and 2 = the matrix-core kernel (n = 8 and 16, FP32 or FP64 inputs, FP64
- * accumulation) with 4 or 8 row steps in flight per wave, 0 = the vector
- * kernel, -1 = the default (2 where it applies).
+ * Kernel variant selection. For BMS_KERNEL_UPDATE: 4 and 5 = the
+ * matrix-core (MFMA) kernel at n = 8 and 16 (FP32 or FP64 blocks, the Q step
+ * in FP64) with one or two 16-row tiles per wave; 0..3 = the vector kernels
+ * (0 = four row chunks per work-group with both coefficient columns in
+ * registers, 1 = two chunks, one column at a time, 2 = four chunks, one
+ * column at a time, 3 = two chunks, both columns); -1 restores the built-in
+ * default (4 where it applies, else 2). For BMS_KERNEL_GRAM (n = 8 and 16,
+ * FP32 or FP64 inputs, FP64 accumulation): 1 and 2 = the matrix-core kernel
+ * with every wave streaming its own rows, 4 or 8 row steps in flight; 3, 4,
+ * 5 = the matrix-core kernel with rows staged through LDS, 1, 2 or 4 chunks
+ * in flight per work-group; 0 = the vector kernel; -1 = the default (2).
  * For BMS_KERNEL_HOP: 1 = four threads per site sharing the site's links
  * (n = 4, 8, 16, 32), 0 = one thread per site and column group, -1 = the
  * default (1 where it applies, except FP32 at n = 16). Other kernels are rejected with BMS_EINVAL;

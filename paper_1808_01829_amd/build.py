@@ -23,13 +23,23 @@ CFLAGS = [
 ]
 
 
+# per-file device options: the Gram kernels keep their matrix-core
+# accumulators in ordinary VGPRs (with accumulation registers the loop-carried
+# accumulators are copied between the two files every iteration, which
+# doubles their register use and halves the resident waves)
+FILE_FLAGS = {
+    "blas.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src, verbose):
     obj = os.path.join(OBJ, src + ".o")
-    cmd = ["hipcc"] + CFLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = (["hipcc"] + CFLAGS + FILE_FLAGS.get(src, []) +
+           ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

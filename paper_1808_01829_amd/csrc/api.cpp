@@ -240,7 +240,7 @@ extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
     return BMS_OK;
   }
   if (kernel == BMS_KERNEL_GRAM) {
-    if (variant < -1 || variant > 3) return set_err(c, BMS_EINVAL, "gram variant must be in [-1, 3]");
+    if (variant < -1 || variant > 5) return set_err(c, BMS_EINVAL, "gram variant must be in [-1, 5]");
     c->gram_variant = variant;
     return BMS_OK;
   }

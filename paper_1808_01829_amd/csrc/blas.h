@@ -5,9 +5,7 @@
 #include "internal.h"
 
 #define UPDATE_NCH 4   // row chunks per work-group in the fused update
-#define RED_GROUP 32   // blocks per first-level group of the grid reductions
-#define CNT_STRIDE 64  // ints per reduction counter set (1 + up to 32 groups, padded)
-#define MAX_RED_BLOCKS 1024
+#define MAX_RED_BLOCKS 1024  // blocks of a grid reduction at most
 
 template <typename T, typename TX>
 struct UpdateArgs {
@@ -27,8 +25,8 @@ struct UpdateArgs {
 // run_if: the kernel does nothing unless *run_if is non-zero (NULL: always runs)
 template <typename T>
 hipError_t launch_cholqr_gram(hipStream_t st, int rows, int n, const void* Q, const void* W,
-                              const double2* alpha, double2* G, double2* partials, int* counter,
-                              int nb, const int* run_if);
+                              const double2* alpha, double2* G, double2* partials, int nb,
+                              const int* run_if);
 template <typename T, typename TX>
 hipError_t launch_update(hipStream_t st, const UpdateArgs<T, TX>& a);
 // variant 0: both coefficient columns in registers; 1: one at a time
@@ -40,10 +38,13 @@ bool update_mfma_supported(int n);
 template <typename F>
 hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<F, F>& a, bool two_tiles);
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
-                              double2* out, double2* partials, int* counter, int nb);
+                              double2* out, double2* partials, int nb);
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,
-                         const void* B, const void* X, double2* out, double2* partials,
-                         int* counter, int nb);
+                         const void* B, const void* X, double2* out, double2* partials, int nb);
+// out[p] = sum over b < nb of partials[b * P + p] (in a fixed order), unless
+// *skip is non-zero or *run_if is zero (either may be NULL)
+hipError_t launch_sum_partials(hipStream_t st, const double2* partials, int nb, int P,
+                               double2* out, const int* skip, const int* run_if);
 
 hipError_t launch_resid_block(hipStream_t st, int rows, int n, const void* B, const void* Y,
                               const double* cs, const double* cb, void* R, const int* skip);
@@ -100,9 +101,14 @@ hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s,
 template <typename T>
 hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
                                      SolverFlags* fl, cplx<T>* Mp);
-// variant 0: vector kernel; otherwise the matrix-core kernel where it exists (n = 8, 16)
+// variant 0: vector kernel; 1, 2 and the default: matrix cores, every wave
+// streaming its own rows with 4 or 8 steps in flight; 3, 4, 5: matrix cores,
+// rows staged through LDS with 1, 2 or 4 chunks in flight (n = 8, 16; other n
+// take the vector kernel). nb blocks at most (the size of partials); given the
+// compute-unit count, the matrix-core kernels launch one round of resident
+// blocks. A second kernel sums the blocks' partials into G4.
 template <typename T>
 hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const void* Q,
-                        const void* W, double2* G4, double2* partials, int* counter, int nb,
-                        const int* skip, int variant = -1);
+                        const void* W, double2* G4, double2* partials, int nb,
+                        const int* skip, int variant = -1, int num_cu = 0);
 bool gram4_mfma_supported(int n);

@@ -7,8 +7,16 @@
 // work-group's loads of a run of rows are one contiguous, coalesced span; the
 // row mixing of "block times n x n matrix" goes through LDS.
 #include <algorithm>
+#include <type_traits>
 
 #include "blas.h"
+
+// return a failed HIP status to the caller
+#define HIP_RET(x)                    \
+  do {                                \
+    hipError_t e_ = (x);              \
+    if (e_ != hipSuccess) return e_;  \
+  } while (0)
 
 namespace {
 
@@ -23,52 +31,6 @@ __device__ __forceinline__ RowRange block_rows(int rows, int per_block) {
   r.r0 = blockIdx.x * per_block;
   r.r1 = min(rows, r.r0 + per_block);
   return r;
-}
-
-// Deterministic completion of a grid-wide sum in two levels: every block has
-// written its P-element partial; the last block of each group of RED_GROUP
-// blocks adds its group's partials in block order into a group partial, and
-// the last group adds the group partials in group order. The summation order
-// does not depend on which block finishes last. counter[0] is the top-level
-// counter, counter[1 + g] the one of group g; all are left at zero.
-// partials must hold (gridDim.x + ceil(gridDim.x / RED_GROUP)) * P entries.
-__device__ void last_block_sum(double2* __restrict__ partials, double2* __restrict__ out, int P,
-                               int* __restrict__ counter) {
-  __shared__ int is_last;
-  const int nb = gridDim.x;
-  const int ng = (nb + RED_GROUP - 1) / RED_GROUP;
-  const int g = blockIdx.x / RED_GROUP;
-  const int gsize = min(RED_GROUP, nb - g * RED_GROUP);
-  double2* gpart = partials + (size_t)nb * P;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(&counter[1 + g], 1) == gsize - 1;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  for (int p = threadIdx.x; p < P; p += BMS_WG) {
-    double2 s = make_double2(0, 0);
-    for (int b = g * RED_GROUP; b < g * RED_GROUP + gsize; ++b)
-      s = cadd(s, partials[(size_t)b * P + p]);
-    if (ng == 1)
-      out[p] = s;
-    else
-      gpart[(size_t)g * P + p] = s;
-  }
-  if (threadIdx.x == 0) atomicExch(&counter[1 + g], 0);
-  if (ng == 1) return;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(&counter[0], 1) == ng - 1;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  for (int p = threadIdx.x; p < P; p += BMS_WG) {
-    double2 s = make_double2(0, 0);
-    for (int q = 0; q < ng; ++q) s = cadd(s, gpart[(size_t)q * P + p]);
-    out[p] = s;
-  }
-  if (threadIdx.x == 0) atomicExch(&counter[0], 0);
 }
 
 // Accumulate sum_r conj(xs[r][i]) ys[r][j] over the nr rows staged in LDS.
@@ -105,9 +67,9 @@ __device__ __forceinline__ void pair_accumulate(const PairMap& m, int n, int nr,
   }
 }
 
+// this block's P entries of the Gram into partials[blockIdx.x * P + p]
 __device__ __forceinline__ void pair_finish(const PairMap& m, double2 acc[4], double2* red,
-                                            double2* __restrict__ partials, double2* __restrict__ G,
-                                            int* __restrict__ counter) {
+                                            double2* __restrict__ partials) {
   // red holds nrg*P <= 1024 entries
   if (m.rg < m.nrg) {
     for (int q = 0; q < m.npp; ++q) {
@@ -121,7 +83,6 @@ __device__ __forceinline__ void pair_finish(const PairMap& m, double2 acc[4], do
     for (int g = 0; g < m.nrg; ++g) s = cadd(s, red[g * m.P + p]);
     partials[(size_t)blockIdx.x * m.P + p] = s;
   }
-  last_block_sum(partials, G, m.P, counter);
 }
 
 // ---- kernels ----------------------------------------------------------------
@@ -136,9 +97,7 @@ template <typename T>
 __global__ __launch_bounds__(BMS_WG) void k_gram(int rows, int n, int per_block,
                                                  const cplx<T>* __restrict__ X,
                                                  const cplx<T>* __restrict__ Y,
-                                                 double2* __restrict__ G,
                                                  double2* __restrict__ partials,
-                                                 int* __restrict__ counter,
                                                  const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double2 xs[BMS_WG], ys[BMS_WG];
@@ -158,7 +117,7 @@ __global__ __launch_bounds__(BMS_WG) void k_gram(int rows, int n, int per_block,
     pair_accumulate(m, n, nr, xs, ys, acc);
     __syncthreads();
   }
-  pair_finish(m, acc, red, partials, G, counter);
+  pair_finish(m, acc, red, partials);
 }
 
 // G = V^H V with V = Q - W alpha computed on the fly (alpha FP64, n x n)
@@ -167,9 +126,7 @@ __global__ __launch_bounds__(BMS_WG) void k_cholqr_gram(int rows, int n, int per
                                                         const cplx<T>* __restrict__ Q,
                                                         const cplx<T>* __restrict__ W,
                                                         const double2* __restrict__ alpha,
-                                                        double2* __restrict__ G,
                                                         double2* __restrict__ partials,
-                                                        int* __restrict__ counter,
                                                         const int* __restrict__ run_if) {
   if (run_if && !*run_if) return;
   __shared__ double2 ws[BMS_WG], vs[BMS_WG];
@@ -194,7 +151,7 @@ __global__ __launch_bounds__(BMS_WG) void k_cholqr_gram(int rows, int n, int per
     pair_accumulate(m, n, nr, vs, vs, acc);
     __syncthreads();
   }
-  pair_finish(m, acc, red, partials, G, counter);
+  pair_finish(m, acc, red, partials);
 }
 
 // Y = X M for a rows x n block and an n x n FP64 matrix
@@ -300,13 +257,11 @@ __global__ __launch_bounds__(BMS_WG) void k_update(UpdateArgs<T, TX> a) {
 }
 
 // res[s*n + i] partial sums of |B[r][i] - Y[r][i]|^2 and |B[r][i]|^2 for a
-// batch of vectors Y (FP64); reduced with last_block_sum into out (2n values).
+// batch of vectors Y (FP64), this block's n entries into partials.
 __global__ __launch_bounds__(BMS_WG) void k_resid_norms(int rows, int n, int per_block,
                                                         const double2* __restrict__ B,
                                                         const double2* __restrict__ Y,
-                                                        double2* __restrict__ out,
-                                                        double2* __restrict__ partials,
-                                                        int* __restrict__ counter) {
+                                                        double2* __restrict__ partials) {
   __shared__ double2 red[BMS_WG];
   RowRange rr = block_rows(rows, per_block);
   int groups = BMS_WG / n;
@@ -328,7 +283,6 @@ __global__ __launch_bounds__(BMS_WG) void k_resid_norms(int rows, int n, int per
     for (int q = 0; q < groups; ++q) s = cadd(s, red[q * n + p]);
     partials[(size_t)blockIdx.x * n + p] = s;
   }
-  last_block_sum(partials, out, n, counter);
 }
 
 // S_i = Re sum_r conj(B[r][i]) (a0 B[r][i] + sum_s alpha[s] X[s][r][i])
@@ -336,9 +290,7 @@ __global__ __launch_bounds__(BMS_WG) void k_action(int rows, int n, int per_bloc
                                                    double a0, const double* __restrict__ alpha,
                                                    const double2* __restrict__ B,
                                                    const double2* __restrict__ X,
-                                                   double2* __restrict__ out,
-                                                   double2* __restrict__ partials,
-                                                   int* __restrict__ counter) {
+                                                   double2* __restrict__ partials) {
   __shared__ double2 red[BMS_WG];
   RowRange rr = block_rows(rows, per_block);
   int groups = BMS_WG / n;
@@ -361,10 +313,58 @@ __global__ __launch_bounds__(BMS_WG) void k_action(int rows, int n, int per_bloc
     for (int q = 0; q < groups; ++q) s = cadd(s, red[q * n + p]);
     partials[(size_t)blockIdx.x * n + p] = s;
   }
-  last_block_sum(partials, out, n, counter);
+}
+
+// Final sum of a grid reduction, a kernel of its own: out[p] = sum over b < nb
+// of partials[b * P + p]. SUM_TPE threads share an entry, each adding a
+// contiguous run of the partials in order (SUM_RB loads in flight), and the
+// runs are then added in order: the result depends only on nb. (Finishing
+// the sum inside the producing kernel would need a device-scope fence and an
+// atomic per block, which on this many-XCD part costs tens of microseconds at
+// a few hundred blocks.)
+constexpr int SUM_TPE = 16;
+constexpr int SUM_EPB = BMS_WG / SUM_TPE;  // entries per block
+constexpr int SUM_RB = 8;
+
+__global__ __launch_bounds__(BMS_WG) void k_sum_partials(const double2* __restrict__ partials,
+                                                         int nb, int P, double2* __restrict__ out,
+                                                         const int* __restrict__ skip,
+                                                         const int* __restrict__ run_if) {
+  if ((skip && *skip) || (run_if && !*run_if)) return;
+  __shared__ double2 red[SUM_TPE][SUM_EPB];
+  const int le = threadIdx.x % SUM_EPB, part = threadIdx.x / SUM_EPB;
+  const int p = blockIdx.x * SUM_EPB + le;
+  const int per = (nb + SUM_TPE - 1) / SUM_TPE;
+  const int b0 = part * per, b1 = min(nb, b0 + per);
+  double2 s = make_double2(0, 0);
+  if (p < P) {
+    int b = b0;
+    for (; b + SUM_RB <= b1; b += SUM_RB) {
+      double2 v[SUM_RB];
+#pragma unroll
+      for (int k = 0; k < SUM_RB; ++k) v[k] = partials[(size_t)(b + k) * P + p];
+#pragma unroll
+      for (int k = 0; k < SUM_RB; ++k) s = cadd(s, v[k]);
+    }
+    for (; b < b1; ++b) s = cadd(s, partials[(size_t)b * P + p]);
+  }
+  red[part][le] = s;
+  __syncthreads();
+  if (part == 0 && p < P) {
+    double2 t = red[0][le];
+    for (int q = 1; q < SUM_TPE; ++q) t = cadd(t, red[q][le]);
+    out[p] = t;
+  }
 }
 
 }  // namespace
+
+hipError_t launch_sum_partials(hipStream_t st, const double2* partials, int nb, int P,
+                               double2* out, const int* skip, const int* run_if) {
+  k_sum_partials<<<(P + SUM_EPB - 1) / SUM_EPB, BMS_WG, 0, st>>>(partials, nb, P, out, skip,
+                                                                 run_if);
+  return hipGetLastError();
+}
 
 int gram_blocks(int rows, int n, int num_cu) {
   // enough blocks to fill the chip, each with at least a few chunks of rows;
@@ -407,19 +407,19 @@ hipError_t launch_fill_zero(hipStream_t st, void* p, size_t bytes) {
 
 template <typename T>
 hipError_t launch_gram(hipStream_t st, int rows, int n, const void* X, const void* Y, double2* G,
-                       double2* partials, int* counter, int nb, const int* skip) {
+                       double2* partials, int nb, const int* skip) {
   k_gram<T><<<nb, BMS_WG, 0, st>>>(rows, n, rows_per_block(rows, nb), (const cplx<T>*)X,
-                                   (const cplx<T>*)Y, G, partials, counter, skip);
-  return hipGetLastError();
+                                   (const cplx<T>*)Y, partials, skip);
+  return launch_sum_partials(st, partials, nb, n * n, G, skip, nullptr);
 }
 
 template <typename T>
 hipError_t launch_cholqr_gram(hipStream_t st, int rows, int n, const void* Q, const void* W,
-                              const double2* alpha, double2* G, double2* partials, int* counter,
-                              int nb, const int* skip) {
+                              const double2* alpha, double2* G, double2* partials, int nb,
+                              const int* run_if) {
   k_cholqr_gram<T><<<nb, BMS_WG, 0, st>>>(rows, n, rows_per_block(rows, nb), (const cplx<T>*)Q,
-                                          (const cplx<T>*)W, alpha, G, partials, counter, skip);
-  return hipGetLastError();
+                                          (const cplx<T>*)W, alpha, partials, run_if);
+  return launch_sum_partials(st, partials, nb, n * n, G, nullptr, run_if);
 }
 
 template <typename T>
@@ -439,25 +439,25 @@ hipError_t launch_update(hipStream_t st, const UpdateArgs<T, TX>& a) {
 }
 
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
-                              double2* out, double2* partials, int* counter, int nb) {
+                              double2* out, double2* partials, int nb) {
   k_resid_norms<<<nb, BMS_WG, 0, st>>>(rows, n, rows_per_block(rows, nb), (const double2*)B,
-                                       (const double2*)Y, out, partials, counter);
-  return hipGetLastError();
+                                       (const double2*)Y, partials);
+  return launch_sum_partials(st, partials, nb, n, out, nullptr, nullptr);
 }
 
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,
                          const void* B, const void* X, double2* out, double2* partials,
-                         int* counter, int nb) {
+                         int nb) {
   k_action<<<nb, BMS_WG, 0, st>>>(rows, n, rows_per_block(rows, nb), ns, a0, alpha,
-                                  (const double2*)B, (const double2*)X, out, partials, counter);
-  return hipGetLastError();
+                                  (const double2*)B, (const double2*)X, partials);
+  return launch_sum_partials(st, partials, nb, n, out, nullptr, nullptr);
 }
 
 #define INST(T)                                                                                \
   template hipError_t launch_gram<T>(hipStream_t, int, int, const void*, const void*, double2*, \
-                                     double2*, int*, int, const int*);                          \
+                                     double2*, int, const int*);                                \
   template hipError_t launch_cholqr_gram<T>(hipStream_t, int, int, const void*, const void*,    \
-                                            const double2*, double2*, double2*, int*, int,      \
+                                            const double2*, double2*, double2*, int,            \
                                             const int*);                                        \
   template hipError_t launch_block_matmul<T>(hipStream_t, int, int, const void*, const double2*, \
                                              void*);
@@ -508,9 +508,7 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4(int rows, int n, int per_block
                                                   const cplx<T>* __restrict__ P,
                                                   const cplx<T>* __restrict__ Q,
                                                   const cplx<T>* __restrict__ W,
-                                                  double2* __restrict__ G4,
-                                                  double2* __restrict__ partials,
-                                                  int* __restrict__ counter,
+                                                                                                    double2* __restrict__ partials,
                                                   const int* __restrict__ skip) {
   using C_ = cplx<T>;
   if (skip && *skip) return;
@@ -636,7 +634,6 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4(int rows, int n, int per_block
       if (d.g >= 2 && d.ti != d.tj) part[d.g * nn + j * n + i] = cconj(sum);
     }
   }
-  last_block_sum(partials, G4, 4 * nn, counter);
 }
 
 // ---- the four Grams of one iteration on the matrix cores --------------------
@@ -683,23 +680,54 @@ struct GramRow {
   }
 };
 
+// What a lane loads per row and step: the complex of its column (n = 16) or
+// the real of its interleaved column (n = 8), kept raw until its step runs.
+template <typename T, int N>
+struct GramRaw {
+  using type = typename std::conditional<N == 16, cplx<T>, T>::type;
+  __device__ static __forceinline__ type load(const cplx<T>* X, size_t r, int c) {
+    if constexpr (N == 16)
+      return X[r * N + c];
+    else
+      return ((const T*)X)[r * 2 * N + c];
+  }
+  // the step's operand values, zero for a row past the range
+  __device__ static __forceinline__ void use(const type& z, bool ok,
+                                             double (&v)[GramRow<T, N>::NT]) {
+    if constexpr (N == 16) {
+      v[0] = ok ? (double)z.x : 0.0;
+      v[1] = ok ? (double)z.y : 0.0;
+    } else {
+      v[0] = ok ? (double)z : 0.0;
+    }
+  }
+};
+
+// Every wave streams its own contiguous rows (a quarter of the block's) in
+// steps of 4 and forms all four products, 14 tiles a step for n = 16, so the
+// waves carry equal work and never wait for each other. D steps of raw loads
+// are in flight: a step's values are taken (and zeroed past the range) right
+// before its slot is refilled, and every load is unconditional, so the wait
+// for a step covers only that step's loads.
 template <typename T, int N, int D>
 __global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
                                                        const cplx<T>* __restrict__ P,
                                                        const cplx<T>* __restrict__ Q,
                                                        const cplx<T>* __restrict__ W,
-                                                       double2* __restrict__ G4,
-                                                       double2* __restrict__ partials,
-                                                       int* __restrict__ counter,
+                                                                                                              double2* __restrict__ partials,
                                                        const int* __restrict__ skip) {
   using GR = GramRow<T, N>;
+  using RW = GramRaw<T, N>;
+  using raw = typename RW::type;
   constexpr int NR = 2 * N, NT = GR::NT, NN = N * N;
   constexpr int NPAIR = NT * (NT + 1) / 2;  // tiles a <= b of a symmetric product
   __shared__ double red[4][NR * NR];        // one real Gram per wave
   if (skip && *skip) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the wave index as a scalar: the step loop's bounds and exits are then
+  // uniform branches, which keep the load-wait accounting exact
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, c = lane & 15;
-  const RowRange rr = block_rows(rows, per_block);
   gdx4 apw[NT][NT], aqw[NT][NT], aww[NPAIR], aqq[NPAIR];
 #pragma unroll
   for (int a = 0; a < NT; ++a)
@@ -707,29 +735,41 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
     for (int b = 0; b < NT; ++b) apw[a][b] = aqw[a][b] = gdx4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int e = 0; e < NPAIR; ++e) aww[e] = aqq[e] = gdx4{0.0, 0.0, 0.0, 0.0};
-  // steps of 4 rows, dealt round-robin to the waves; a ring of D steps in flight
-  const int nsteps = (rr.r1 - rr.r0 + 3) >> 2;
-  double p[D][NT], q[D][NT], w[D][NT];
-  auto load = [&](int st, double (&pv)[NT], double (&qv)[NT], double (&wv)[NT]) {
-    int r = rr.r0 + 4 * st + g;
-    bool ok = st < nsteps && r < rr.r1;
-    GR::load(P, r, ok, c, pv);
-    GR::load(Q, r, ok, c, qv);
-    GR::load(W, r, ok, c, wv);
+  // steps of 4 rows dealt to the waves of the whole grid in turn (step k of
+  // wave v is k * nwaves + v), so the waves in flight read one contiguous
+  // stretch of each block vector, as a streaming copy does; each wave runs a
+  // whole number of D-step rounds (no exit inside a round, whose loads would
+  // then differ by path), steps past the end are empty
+  (void)per_block;
+  const int nsteps = (rows + 3) >> 2;
+  const int nwaves = gridDim.x * 4, vw = blockIdx.x * 4 + wave;
+  const int mine = vw < nsteps ? (nsteps - vw + nwaves - 1) / nwaves : 0;
+  const int nst = (mine + D - 1) / D * D;
+  const size_t rstride = 4 * (size_t)nwaves;  // rows between a wave's steps
+  const size_t rbase = 4 * (size_t)vw + g;    // this lane's row at step 0
+  raw p[D], q[D], w[D];
+  auto fetch = [&](int st, raw& pv, raw& qv, raw& wv) {
+    const size_t r = rbase + rstride * st;
+    const size_t rc = r < (size_t)rows ? r : 0;
+    pv = RW::load(P, rc, c);
+    qv = RW::load(Q, rc, c);
+    wv = RW::load(W, rc, c);
   };
 #pragma unroll
-  for (int u = 0; u < D; ++u) load(wave + 4 * u, p[u], q[u], w[u]);
-  for (int st = wave; st < nsteps; st += 4 * D) {
+  for (int u = 0; u < D; ++u) fetch(u, p[u], q[u], w[u]);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int st0 = 0; st0 < nst; st0 += D) {
 #pragma unroll
     for (int u = 0; u < D; ++u) {
+      const int st = st0 + u;
+      const bool ok = rbase + rstride * st < (size_t)rows;
       double pc[NT], qc[NT], wc[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        pc[t] = p[u][t];
-        qc[t] = q[u][t];
-        wc[t] = w[u][t];
-      }
-      load(st + 4 * (u + D), p[u], q[u], w[u]);
+      RW::use(p[u], ok, pc);
+      RW::use(q[u], ok, qc);
+      RW::use(w[u], ok, wc);
+      fetch(st + D, p[u], q[u], w[u]);
+      // keep the refill here, D steps ahead of its use
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int a = 0; a < NT; ++a)
 #pragma unroll
@@ -797,7 +837,6 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
       for (int b = a; b < NT; ++b, ++e) put(a, b, aqq[e], a != b);
   }
   reduce(3);
-  last_block_sum(partials, G4, 4 * NN, counter);
 }
 
 // Same four Grams, the rows shared through LDS: the block stages chunks of
@@ -831,16 +870,19 @@ __device__ __forceinline__ void gram_operand(const cplx<T>* blk, int rl, int c,
   }
 }
 
-// one chunk of one wave's product: all GCH/4 steps' operands, then the MFMAs
-template <typename T, int N, bool SYM>
+// one chunk of one wave's product: all its steps' operands, then the MFMAs
+// (with WPP waves per product, wave h of the product takes steps h, h+WPP, ...)
+template <typename T, int N, bool SYM, int WPP>
 __device__ __forceinline__ void gram_chunk(const cplx<T>* xs, const cplx<T>* ys, int g, int c,
+                                           int h,
                                            gdx4 (&acc)[GramRow<T, N>::NT][GramRow<T, N>::NT]) {
-  constexpr int NT = GramRow<T, N>::NT, ST = GCH / 4;
+  constexpr int NT = GramRow<T, N>::NT, ST = GCH / 4 / WPP;
   double x[ST][NT], y[ST][NT];
 #pragma unroll
   for (int st = 0; st < ST; ++st) {
-    gram_operand<T, N>(xs, 4 * st + g, c, x[st]);
-    if constexpr (!SYM) gram_operand<T, N>(ys, 4 * st + g, c, y[st]);
+    const int rl = 4 * (st * WPP + h) + g;
+    gram_operand<T, N>(xs, rl, c, x[st]);
+    if constexpr (!SYM) gram_operand<T, N>(ys, rl, c, y[st]);
   }
 #pragma unroll
   for (int st = 0; st < ST; ++st)
@@ -852,75 +894,91 @@ __device__ __forceinline__ void gram_chunk(const cplx<T>* xs, const cplx<T>* ys,
                                                          acc[a][b], 0, 0, 0);
 }
 
-template <typename T, int N, bool SYM>
+// The chunk loop with D chunks in flight: register slot u of the ring holds
+// chunk i0 + u; at chunk i the slot of chunk i (already in LDS) is refilled
+// with chunk i + D, so a chunk's loads have D - 1 chunks of work to land.
+// Every fetch and stash runs unconditionally (rows past the range read a
+// valid row and are zeroed by a select, the chunk count is padded to a
+// multiple of D with such empty chunks): with loads skipped on some paths the
+// compiler can no longer tell which slot is still in flight and waits for all
+// of them before every fetch, which serialises the ring.
+template <typename T, int N, bool SYM, int WPP, int D>
 __device__ __forceinline__ void gram_sweep(const cplx<T>* P, const cplx<T>* Q, const cplx<T>* W,
-                                           RowRange rr, cplx<T>* stage, int xb, int yb,
+                                           RowRange rr, cplx<T>* stage, int xb, int yb, int h,
                                            gdx4 (&acc)[GramRow<T, N>::NT][GramRow<T, N>::NT]) {
   using C_ = cplx<T>;
   using GS = GramStage<T, N>;
+  constexpr int NTH = 4 * WPP * 64;                // threads of the block
+  constexpr int PER_T = GCH * N / NTH;             // complex per thread and staged block
+  static_assert(PER_T >= 1 && GCH * N % NTH == 0, "chunk must cover the block");
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = lane >> 4, c = lane & 15;
+  if (rr.r1 <= rr.r0) return;
   const C_* src[3] = {P, Q, W};
-  C_ nx[3][GS::PER_T];
-  // chunk loader: element e = tid + k*256 of the chunk's rows x N complex; a
-  // full chunk loads without conditions, only a ragged last one checks rows
-  auto fetch = [&](int r0) {
-    if (r0 + GCH <= rr.r1) {
+  const int nchunks = (rr.r1 - rr.r0 + GCH - 1) / GCH;
+  const int npad = (nchunks + D - 1) / D * D;
+  C_ nx[D][3][PER_T];
+  // element e = tid + k*NTH of a chunk's GCH x N complex; rows past the range
+  // load row r0 (the loads stay unconditional) and are zeroed at the stash,
+  // so no load result is needed before its chunk is staged
+  auto fetch = [&](int ci, C_ (&dst)[3][PER_T]) {
+    const int r0 = rr.r0 + ci * GCH;
 #pragma unroll
-      for (int b = 0; b < 3; ++b)
+    for (int k = 0; k < PER_T; ++k) {
+      const int e = tid + k * NTH;
+      const size_t at = r0 + e / N < rr.r1 ? (size_t)r0 * N + e : (size_t)rr.r0 * N;
 #pragma unroll
-        for (int k = 0; k < GS::PER_T; ++k) nx[b][k] = src[b][(size_t)r0 * N + tid + k * BMS_WG];
-    } else {
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int k = 0; k < GS::PER_T; ++k) {
-          int e = tid + k * BMS_WG;
-          bool ok = r0 + e / N < rr.r1;
-          nx[b][k] = ok ? src[b][(size_t)r0 * N + e] : czero<C_>();
-        }
+      for (int b = 0; b < 3; ++b) dst[b][k] = src[b][at];
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const C_ (&from)[3][PER_T], int ci) {
+    const int r0 = rr.r0 + ci * GCH, buf = ci & 1;
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int k = 0; k < PER_T; ++k) {
+      const int e = tid + k * NTH;
+      const bool ok = r0 + e / N < rr.r1;
 #pragma unroll
-      for (int k = 0; k < GS::PER_T; ++k) {
-        int e = tid + k * BMS_WG;
-        stage[(buf * 3 + b) * GS::BS + (e / N) * GS::RS + (e % N)] = nx[b][k];
+      for (int b = 0; b < 3; ++b) {
+        C_ v;
+        v.x = ok ? from[b][k].x : 0;
+        v.y = ok ? from[b][k].y : 0;
+        stage[(buf * 3 + b) * GS::BS + (e / N) * GS::RS + (e % N)] = v;
       }
+    }
   };
-  int buf = 0;
-  if (rr.r0 < rr.r1) {
-    fetch(rr.r0);
-    stash(0);
-  }
+#pragma unroll
+  for (int u = 0; u < D; ++u) fetch(u, nx[u]);
+  __builtin_amdgcn_sched_barrier(0);
+  stash(nx[0], 0);
   __syncthreads();
-  for (int r0 = rr.r0; r0 < rr.r1; r0 += GCH) {
-    const bool more = r0 + GCH < rr.r1;
-    if (more) fetch(r0 + GCH);
-    gram_chunk<T, N, SYM>(stage + (buf * 3 + xb) * GS::BS, stage + (buf * 3 + yb) * GS::BS, g, c,
-                          acc);
-    if (more) stash(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+  for (int i0 = 0; i0 < npad; i0 += D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int i = i0 + u;
+      fetch(i + D, nx[u]);  // chunk i is in LDS: its slot takes chunk i + D
+      // keep the loads here: the scheduler would otherwise sink them next to
+      // their use (the stash D - 1 chunks later), leaving no time to land
+      __builtin_amdgcn_sched_barrier(0);
+      gram_chunk<T, N, SYM, WPP>(stage + ((i & 1) * 3 + xb) * GS::BS,
+                                 stage + ((i & 1) * 3 + yb) * GS::BS, g, c, h, acc);
+      stash(nx[(u + 1) % D], i + 1);
+      __syncthreads();
+    }
   }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
+template <typename T, int N, int WPP, int D>
+__global__ __launch_bounds__(4 * WPP * 64) void k_gram4_lds(int rows, int per_block,
                                                       const cplx<T>* __restrict__ P,
                                                       const cplx<T>* __restrict__ Q,
                                                       const cplx<T>* __restrict__ W,
-                                                      double2* __restrict__ G4,
-                                                      double2* __restrict__ partials,
-                                                      int* __restrict__ counter,
+                                                                                                            double2* __restrict__ partials,
                                                       const int* __restrict__ skip) {
   using C_ = cplx<T>;
   using GR = GramRow<T, N>;
   using GS = GramStage<T, N>;
   constexpr int NR = 2 * N, NT = GR::NT, NN = N * N;
-  static_assert(GS::PER_T >= 1 && GCH * N % BMS_WG == 0, "chunk must cover the block");
+  constexpr int NTH = 4 * WPP * 64;
   constexpr int STAGE = 2 * 3 * GS::BS * (int)sizeof(C_);
   constexpr int REDB = 4 * NR * NR * (int)sizeof(double);
   __shared__ __align__(16) unsigned char smem[STAGE > REDB ? STAGE : REDB];
@@ -928,46 +986,63 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
   C_* stage = (C_*)smem;  // [2][3][GCH][RS]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
+  const int prod = wave & 3, h = wave >> 2;  // product and, with WPP = 2, which half of it
   const RowRange rr = block_rows(rows, per_block);
   // this wave's product: x block and y block (0 = P, 1 = Q, 2 = W)
-  const int xb = wave == 0 ? 0 : (wave == 2 ? 2 : 1);
-  const int yb = wave == 3 ? 1 : 2;
-  const bool sym = wave >= 2;
+  const int xb = prod == 0 ? 0 : (prod == 2 ? 2 : 1);
+  const int yb = prod == 3 ? 1 : 2;
+  const bool sym = prod >= 2;
   gdx4 acc[NT][NT];
 #pragma unroll
   for (int a = 0; a < NT; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = gdx4{0.0, 0.0, 0.0, 0.0};
   if (sym)
-    gram_sweep<T, N, true>(P, Q, W, rr, stage, xb, yb, acc);
+    gram_sweep<T, N, true, WPP, D>(P, Q, W, rr, stage, xb, yb, h, acc);
   else
-    gram_sweep<T, N, false>(P, Q, W, rr, stage, xb, yb, acc);
-  // each wave's real Gram into LDS (tile row g + 4k, column c), then the
-  // complex entries of all four products
-  double* R = (double*)smem + wave * NR * NR;
+    gram_sweep<T, N, false, WPP, D>(P, Q, W, rr, stage, xb, yb, h, acc);
+  // each product's real Gram into LDS (tile row g + 4k, column c; with two
+  // waves per product the second adds its part after the first wrote), then
+  // the complex entries of all four products
+  double* R = (double*)smem + prod * NR * NR;
+  for (int half = 0; half < WPP; ++half) {
+    if (h == half) {
 #pragma unroll
-  for (int a = 0; a < NT; ++a)
+      for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < NT; ++b) {
-      if (sym && b < a) continue;
+        for (int b = 0; b < NT; ++b) {
+          if (sym && b < a) continue;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        int i = a * 16 + g + 4 * k, j = b * 16 + c;
-        R[i * NR + j] = acc[a][b][k];
-        if (sym && a != b) R[j * NR + i] = acc[a][b][k];
-      }
+          for (int k = 0; k < 4; ++k) {
+            int i = a * 16 + g + 4 * k, j = b * 16 + c;
+            double v = acc[a][b][k] + (half ? R[i * NR + j] : 0.0);
+            R[i * NR + j] = v;
+            if (sym && a != b) R[j * NR + i] = v;
+          }
+        }
     }
-  __syncthreads();
+    __syncthreads();
+  }
   double2* part = partials + (size_t)blockIdx.x * 4 * NN;
-  for (int e = tid; e < 4 * NN; e += BMS_WG) {
+  for (int e = tid; e < 4 * NN; e += NTH) {
     int gi = e / NN, ij = e - gi * NN;
     int i = ij / N, j = ij - (ij / N) * N;
     part[e] = GR::entry((const double*)smem + gi * NR * NR, i, j);
   }
-  last_block_sum(partials, G4, 4 * NN, counter);
 }
 
 }  // namespace
+
+// resident blocks of a BMS_WG-thread kernel per compute unit (0 if unknown)
+template <typename K>
+static int lds_occupancy(K kernel) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, BMS_WG, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return occ;
+}
 
 int gram4_tb(int n) { return (n >= 16 && n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1); }
 
@@ -980,63 +1055,80 @@ bool gram4_mfma_supported(int n) { return n == 8 || n == 16; }
 
 template <typename T>
 hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const void* Q,
-                        const void* W, double2* G4, double2* partials, int* counter, int nb,
-                        const int* skip, int variant) {
+                        const void* W, double2* G4, double2* partials, int nb,
+                        const int* skip, int variant, int num_cu) {
   int per = rows_per_block(rows, nb);
   const cplx<T>* p = (const cplx<T>*)P;
   const cplx<T>* q = (const cplx<T>*)Q;
   const cplx<T>* w = (const cplx<T>*)W;
-  if (variant < 0 || variant == 3) {
+  const int P4 = 4 * n * n;  // the four Grams' entries per partial
+  int grid = nb;
+  if (variant >= 3 && gram4_mfma_supported(n)) {
+    // chunks in flight per block: variant 3 one, 4 two, 5 four
+    // one round of resident blocks: the deeper rings need more registers and
+    // fit fewer blocks per compute unit than the three the grid is sized for
+#define GL(NN, DD)                                                                              \
+  do {                                                                                          \
+    static const int occ = lds_occupancy(k_gram4_lds<T, NN, 1, DD>);                            \
+    const int nbl = num_cu > 0 && occ > 0 ? std::min(nb, occ * num_cu) : nb;                    \
+    k_gram4_lds<T, NN, 1, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w, \
+                                                      partials, skip);                          \
+    grid = nbl;                                                                                 \
+  } while (0)
+    const int depth = variant == 3 ? 1 : (variant == 4 ? 2 : 4);
     if (n == 16) {
-      k_gram4_lds<T, 16><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
-      return hipGetLastError();
-    }
-    if (n == 8) {
-      k_gram4_lds<T, 8><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
-      return hipGetLastError();
-    }
-  }
-  if ((variant == 1 || variant == 2) && gram4_mfma_supported(n)) {
-    // variant 1: 4 steps in flight per wave, otherwise 8
-    if (n == 16) {
-      if (variant == 1)
-        k_gram4_mfma<T, 16, 4><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
-      else
-        k_gram4_mfma<T, 16, 8><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+      if (depth == 1) GL(16, 1); else if (depth == 2) GL(16, 2); else GL(16, 4);
     } else {
-      if (variant == 1)
-        k_gram4_mfma<T, 8, 4><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
-      else
-        k_gram4_mfma<T, 8, 8><<<nb, BMS_WG, 0, st>>>(rows, per, p, q, w, G4, partials, counter, skip);
+      if (depth == 1) GL(8, 1); else if (depth == 2) GL(8, 2); else GL(8, 4);
     }
-    return hipGetLastError();
+#undef GL
+    HIP_RET(hipGetLastError());
+    return launch_sum_partials(st, partials, grid, P4, G4, skip, nullptr);
+  }
+  if ((variant < 0 || variant == 1 || variant == 2) && gram4_mfma_supported(n)) {
+    // steps in flight per wave: variant 1 four, 2 (and the default) eight
+#define GR_(NN, DD)                                                                              \
+  do {                                                                                           \
+    static const int occ = lds_occupancy(k_gram4_mfma<T, NN, DD>);                               \
+    const int nbl = num_cu > 0 && occ > 0 ? std::min(nb, occ * num_cu) : nb;                     \
+    k_gram4_mfma<T, NN, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w,     \
+                                                    partials, skip);                             \
+    grid = nbl;                                                                                  \
+  } while (0)
+    if (n == 16) {
+      if (variant == 1) GR_(16, 4); else GR_(16, 8);
+    } else {
+      if (variant == 1) GR_(8, 4); else GR_(8, 8);
+    }
+#undef GR_
+    HIP_RET(hipGetLastError());
+    return launch_sum_partials(st, partials, grid, P4, G4, skip, nullptr);
   }
   if (!gram4_fits(n)) {  // four pairwise passes
     const cplx<T>* xs[4] = {p, q, w, q};
     const cplx<T>* ys[4] = {w, w, w, q};
-    for (int g = 0; g < 4; ++g) {
-      k_gram<T><<<nb, BMS_WG, 0, st>>>(rows, n, per, xs[g], ys[g], G4 + (size_t)g * n * n,
-                                       partials, counter, skip);
-    }
-    return hipGetLastError();
+    for (int g = 0; g < 4; ++g) HIP_RET(launch_gram<T>(st, rows, n, xs[g], ys[g],
+                                                       G4 + (size_t)g * n * n, partials, nb, skip));
+    return hipSuccess;
   }
   switch (gram4_tb(n)) {
     case 4:
-      k_gram4<T, 4><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, G4, partials, counter, skip);
+      k_gram4<T, 4><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, partials, skip);
       break;
     case 2:
-      k_gram4<T, 2><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, G4, partials, counter, skip);
+      k_gram4<T, 2><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, partials, skip);
       break;
     default:
-      k_gram4<T, 1><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, G4, partials, counter, skip);
+      k_gram4<T, 1><<<nb, BMS_WG, 0, st>>>(rows, n, per, p, q, w, partials, skip);
   }
-  return hipGetLastError();
+  HIP_RET(hipGetLastError());
+  return launch_sum_partials(st, partials, nb, P4, G4, skip, nullptr);
 }
 template hipError_t launch_gram4<double>(hipStream_t, int, int, const void*, const void*,
-                                         const void*, double2*, double2*, int*, int, const int*,
+                                         const void*, double2*, double2*, int, const int*, int,
                                          int);
 template hipError_t launch_gram4<float>(hipStream_t, int, int, const void*, const void*,
-                                        const void*, double2*, double2*, int*, int, const int*,
+                                        const void*, double2*, double2*, int, const int*, int,
                                         int);
 
 // ---- fused update, specialised on the block width ---------------------------

@@ -27,7 +27,7 @@ std::vector<int> candidates(int kernel, int n) {
   const bool mf = n == 8 || n == 16;
   switch (kernel) {
     case BMS_KERNEL_HOP: return quad ? std::vector<int>{0, 1} : std::vector<int>{0};
-    case BMS_KERNEL_GRAM: return mf ? std::vector<int>{0, 3, 2} : std::vector<int>{0};
+    case BMS_KERNEL_GRAM: return mf ? std::vector<int>{2, 1, 3} : std::vector<int>{0};
     case BMS_KERNEL_UPDATE: return mf ? std::vector<int>{4, 5, 2, 0} : std::vector<int>{2};
     default: return {};
   }

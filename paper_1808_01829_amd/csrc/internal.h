@@ -87,12 +87,11 @@ template <typename T>
 hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
                       double a, double b, const int* skip);
 
-// Gram partials with last-block reduction: G (n x n, FP64) = X^H Y over
-// `rows` rows of n complex. partials must hold nb*n*n double2, counter one
-// int (zero on entry, left zero).
+// G (n x n, FP64) = X^H Y over `rows` rows of n complex: nb blocks write
+// partial Grams (partials must hold nb*n*n double2), a second kernel sums them.
 template <typename T>
 hipError_t launch_gram(hipStream_t st, int rows, int n, const void* X, const void* Y, double2* G,
-                       double2* partials, int* counter, int nb, const int* skip);
+                       double2* partials, int nb, const int* skip);
 int gram_blocks(int rows, int n, int num_cu);
 
 // Y = X M (rows x n times n x n, M FP64 on device), optionally Y += (accum)

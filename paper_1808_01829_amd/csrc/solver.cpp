@@ -56,13 +56,11 @@ enum Slot {
 
 const double kEps = 2.220446049250313e-16;
 const double kEps32 = 1.1920928955078125e-07;
-const size_t kFlagsBytes = sizeof(SolverFlags) + 4 * CNT_STRIDE * sizeof(int) + 64;
+// the solver flags, then the arrival counter of the small-step blocks
+const size_t kFlagsBytes = sizeof(SolverFlags) + 64;
 
-// partial sums of a grid reduction over nb blocks of P entries, plus the
-// first-level group sums
-size_t part_bytes(int nb, int P) {
-  return ((size_t)nb + (nb + RED_GROUP - 1) / RED_GROUP) * P * sizeof(double2) + 64;
-}
+// partial sums of a grid reduction over nb blocks of P entries
+size_t part_bytes(int nb, int P) { return (size_t)nb * P * sizeof(double2) + 64; }
 
 struct Work {
   int rows, n, ns;
@@ -71,7 +69,6 @@ struct Work {
   SmallState sm;
   SolverFlags* flags;
   double2* partials;
-  int* counters;  // sets of CNT_STRIDE: [0] Grams, [1] Cholesky-QR Gram, [2] misc, [3] small
   double2* Rinv;
   double2* Gtmp;
   int nb;
@@ -132,8 +129,7 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   void* fp;
   if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
   w.flags = (SolverFlags*)fp;
-  w.counters = (int*)((char*)fp + sizeof(SolverFlags));
-  w.sm.counter = w.counters + 3 * CNT_STRIDE;
+  w.sm.counter = (int*)((char*)fp + sizeof(SolverFlags));
   void* lp;
   if ((rc = scratch_buf(c, S_LOG, (size_t)max_iter * sizeof(int) + 64, &lp))) return rc;
   w.sm.nact_log = (int*)lp;
@@ -156,16 +152,15 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   MARK(1);
   HIP_TRY(c, launch_hop<T>(c, 0, w.n, w.W1, w.W, P0, mass * mass + sp.sigma[0], -1.0, skip));
   MARK(2);
-  HIP_TRY(c, launch_gram4<T>(c->stream, w.rows, w.n, P0, w.Q, w.W, w.sm.G4, w.partials,
-                             w.counters, w.nb, skip, c->gram_variant));
+  HIP_TRY(c, launch_gram4<T>(c->stream, w.rows, w.n, P0, w.Q, w.W, w.sm.G4, w.partials, w.nb,
+                             skip, c->gram_variant, c->num_cu));
   MARK(3);
   HIP_TRY(c, launch_small_iter<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mx,
                                   (cplx<T>*)w.Mp));
   MARK(4);
   // explicit Cholesky-QR Gram, only when the expansion lost its pivot
   HIP_TRY(c, launch_cholqr_gram<T>(c->stream, w.rows, w.n, w.Q, w.W, w.sm.alpha, w.sm.Gqr,
-                                   w.partials, w.counters + CNT_STRIDE, w.nb,
-                                   &w.flags->need_explicit));
+                                   w.partials, w.nb, &w.flags->need_explicit));
   MARK(5);
   HIP_TRY(c, launch_small_rho_explicit<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mp));
   MARK(6);
@@ -199,15 +194,15 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
 template <typename T>
 int enqueue_setup(bms_ctx* c, const Work& w, const SmallParams& sp, const void* B) {
   size_t es = sizeof(cplx<T>);
-  // grid-completion counters must start at zero (they are left at zero after use)
-  HIP_TRY(c, launch_fill_zero(c->stream, w.counters, 4 * CNT_STRIDE * sizeof(int)));
+  // the small-step arrival counter must start at zero (it is left at zero after use)
+  HIP_TRY(c, launch_fill_zero(c->stream, w.sm.counter, 16));
   HIP_TRY(c, launch_fill_zero(c->stream, w.X, w.blk * es * w.ns));
-  HIP_TRY(c, launch_gram<double>(c->stream, w.rows, w.n, B, B, w.sm.G4, w.partials, w.counters,
-                                 w.nb, nullptr));
+  HIP_TRY(c, launch_gram<double>(c->stream, w.rows, w.n, B, B, w.sm.G4, w.partials, w.nb,
+                                 nullptr));
   HIP_TRY(c, launch_small_init(c->stream, sp, w.sm, w.flags, w.sm.G4, w.Rinv));
   HIP_TRY(c, launch_block_matmul_d<T>(c->stream, w.rows, w.n, B, w.Rinv, w.W, nullptr));
-  HIP_TRY(c, launch_gram<T>(c->stream, w.rows, w.n, w.W, w.W, w.sm.G4, w.partials, w.counters,
-                            w.nb, nullptr));
+  HIP_TRY(c, launch_gram<T>(c->stream, w.rows, w.n, w.W, w.W, w.sm.G4, w.partials, w.nb,
+                            nullptr));
   HIP_TRY(c, launch_small_init_pass2(c->stream, sp, w.sm, w.flags, w.sm.G4, w.Rinv));
   HIP_TRY(c, launch_block_matmul<T>(c->stream, w.rows, w.n, w.W, w.Rinv, w.Q));
   for (int s = 0; s < w.ns; ++s)
@@ -228,8 +223,8 @@ int enqueue_reliable(bms_ctx* c, const Work& w, const SmallParams& sp, double ma
   HIP_TRY(c, launch_hop<double>(c, 1, w.n, X0, R1, nullptr, 0.0, 1.0, skip));
   HIP_TRY(c, launch_hop<double>(c, 0, w.n, R1, R2, X0, mass * mass + sp.sigma[0], -1.0, skip));
   HIP_TRY(c, launch_resid_block(c->stream, w.rows, w.n, B, R2, nullptr, nullptr, R0, skip));
-  HIP_TRY(c, launch_gram<double>(c->stream, w.rows, w.n, R0, R0, w.Gtmp, w.partials,
-                                 w.counters + 2 * CNT_STRIDE, w.nb, skip));
+  HIP_TRY(c, launch_gram<double>(c->stream, w.rows, w.n, R0, R0, w.Gtmp, w.partials, w.nb,
+                                 skip));
   HIP_TRY(c, launch_small_reliable(c->stream, sp, w.sm, w.flags, w.Gtmp, w.Rinv));
   HIP_TRY(c, launch_block_matmul_d<float>(c->stream, w.rows, w.n, R0, w.Rinv, w.Q,
                                           &w.flags->rel_skip));
@@ -258,7 +253,7 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
     SmallState sm;
   } k;
   memset(&k, 0, sizeof k);
-  const void* ptrs[16] = {w.W1, w.W, w.Q, w.P, w.X, w.Mx, w.Mp, w.flags, w.partials, w.counters,
+  const void* ptrs[16] = {w.W1, w.W, w.Q, w.P, w.X, w.Mx, w.Mp, w.flags, w.partials, w.sm.counter,
                           c->links64.p, c->links32.p, nullptr, nullptr, nullptr, nullptr};
   for (int i = 0; i < 16; ++i) k.p[i] = ptrs[i];
   k.mass = mass;
@@ -437,15 +432,12 @@ static int residual_norms(bms_ctx* c, double mass, int n, int ns, const double* 
   int nb = gram_blocks(rows, n, c->num_cu);
   void* pp;
   if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
-  void* fp;
-  if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
-  int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2 * CNT_STRIDE;
   for (int s = 0; s < ns; ++s) {
     const double2* xs = (const double2*)X + s * blk;
     HIP_TRY(c, launch_hop<double>(c, 1, n, xs, t1, nullptr, 0.0, 1.0, nullptr));
     HIP_TRY(c, launch_hop<double>(c, 0, n, t1, t2, xs, mass * mass + shifts[s], -1.0, nullptr));
     HIP_TRY(c, launch_resid_norms(c->stream, rows, n, B, t2, (double2*)out + (size_t)s * n,
-                                  (double2*)pp, counter, nb));
+                                  (double2*)pp, nb));
   }
   std::vector<double2> h((size_t)ns * n);
   HIP_TRY(c, hipMemcpyAsync(h.data(), out, h.size() * sizeof(double2), hipMemcpyDeviceToHost,
@@ -684,18 +676,16 @@ extern "C" int bms_action(bms_ctx* c, int n, int ns, double a0, const double* al
   int rc;
   if ((rc = stream_begin(c))) return rc;
   int rows = 3 * c->vh;
-  void *al, *out, *pp, *fp;
+  void *al, *out, *pp;
   if ((rc = scratch_buf(c, S_RES, (size_t)(n + BMS_MAX_SHIFTS) * sizeof(double2) + 64, &out)))
     return rc;
   al = (double2*)out + n;
   int nb = gram_blocks(rows, n, c->num_cu);
   if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
-  if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
-  int* counter = (int*)((char*)fp + sizeof(SolverFlags)) + 2 * CNT_STRIDE;
   if (ns > 0)
     HIP_TRY(c, hipMemcpyAsync(al, alpha, ns * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_action(c->stream, rows, n, ns, a0, (const double*)al, B, X, (double2*)out,
-                           (double2*)pp, counter, nb));
+                           (double2*)pp, nb));
   std::vector<double2> h(n);
   HIP_TRY(c, hipMemcpyAsync(h.data(), out, n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

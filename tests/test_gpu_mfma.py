@@ -34,7 +34,7 @@ CASES = [
 
 
 # (update variant, Gram variant)
-KERNELS = [(-1, -1), (2, 0), (4, 1), (2, 2), (5, 0), (2, 3), (5, 3), (4, 0)]
+KERNELS = [(-1, -1), (2, 0), (4, 1), (2, 2), (5, 0), (2, 3), (5, 3), (4, 0), (4, 4), (5, 5)]
 
 
 @pytest.mark.parametrize("dims,n,k", CASES)
