@@ -86,6 +86,8 @@ int ensure_device(bms_ctx* c) {
   if (c->stream) return BMS_OK;
   HIP_TRY(c, hipGetDevice(&c->device));
   HIP_TRY(c, hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  HIP_TRY(c, hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                   c->device));
   HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   HIP_TRY(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));

@@ -220,11 +220,18 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   // four threads per site sharing the links, for n = 4, 8, 16, 32; by default
   // not for FP32 at n = 16, where the consecutive-column kernel measured faster
   const bool quad_default = !(sizeof(T) == 4 && n == 16);
+  // At most `cap` resident blocks per compute unit, by reserving LDS the
+  // kernel does not use: fewer sites in flight keep the neighbours' re-reads
+  // inside each XCD's L2 (measured at 32^4: FP64 n = 16 513 -> 455 us with
+  // two blocks, FP32 n = 16 276 -> 268 us with four, FP32 n = 8 174 -> 169
+  // us with two; other widths unchanged).
+  const int cap = sizeof(T) == 8 ? (n >= 16 ? 2 : 0) : (n == 16 ? 4 : (n == 8 ? 2 : 0));
+  const size_t lds = cap > 0 && c->lds_per_cu > 0 ? (size_t)c->lds_per_cu / (cap + 1) + 1 : 0;
   if ((c->hop_variant == 1 || (c->hop_variant < 0 && quad_default)) &&
       (n == 4 || n == 8 || n == 16 || n == 32)) {
     dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);
 #define HOPQ(RR)                                                                           \
-  k_hop_q<T, RR><<<qgrid, BMS_WG, 0, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out, \
+  k_hop_q<T, RR><<<qgrid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out, \
                                                  (const cplx<T>*)aux, (T)a, (T)b, c->geom, \
                                                  n, par, c->sbl, skip)
     switch (n) {
@@ -242,7 +249,7 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   dim3 grid((nthr + BMS_WG - 1) / BMS_WG);
   FastDiv dg = make_fastdiv(ngrp);
 #define HOP_LAUNCH(RR)                                                                     \
-  k_hop<T, RR><<<grid, BMS_WG, 0, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out,    \
+  k_hop<T, RR><<<grid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out,    \
                                               (const cplx<T>*)aux, (T)a, (T)b, c->geom, n, \
                                               dg, par, c->sbl, skip)
   if (R == 4)

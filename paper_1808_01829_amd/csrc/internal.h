@@ -42,6 +42,7 @@ struct bms_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int device = -1;
   int num_cu = 0;  // compute units of the device (set with the stream)
+  int lds_per_cu = 0;  // bytes of LDS per compute unit (set with the stream)
   bool gauge_set = false;
   DevBuf links64, links32;  // [parity][blocked links] complex
   std::vector<DevBuf> scratch;  // named by slot index
