@@ -84,6 +84,11 @@ typedef struct bms_opts {
   int use_graph;          /* replay each chunk of check_interval iterations from a
                              captured hipGraph (1, default), or launch directly (0);
                              chunks launch directly while timing is enabled */
+  double mixed_switch;    /* MIXED: relative residual of the smallest shift at which
+                             the FP64 block multi-shift phase hands over to the
+                             FP32 one (3e-4); the FP32 phase solves for the
+                             remaining residual of every unconverged shift at once.
+                             <= tol, or >= 1: FP32 from the start */
 } bms_opts;
 
 /* Solver statistics (filled on BMS_OK, BMS_ENOCONV and BMS_EBREAKDOWN). */
@@ -91,7 +96,8 @@ typedef struct bms_stats {
   int iterations;          /* block iterations of the multi-shift solve */
   int hop_calls;           /* half-hop applications of n-wide (or wider) blocks */
   int reliable_updates;    /* MIXED: FP64 residual replacements */
-  int refine_iterations;   /* MIXED: block iterations spent in defect correction */
+  int refine_iterations;   /* MIXED: block iterations after the first phase (the FP32
+                              multi-shift phase and the defect correction) */
   int converged;           /* 1 if every shift and column met tol (true FP64 residual) */
   double max_true_residual;/* max over shifts and columns of |b - (A+s)x| / |b| */
   double* true_residual;   /* optional caller array [n_shifts][n]; NULL to skip */

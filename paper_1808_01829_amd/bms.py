@@ -49,7 +49,7 @@ class bms_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("reliable_interval", ctypes.c_int),
                 ("freeze_tol", ctypes.c_double), ("check_interval", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("qr_passes", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("mixed_switch", ctypes.c_double)]
 
 
 class bms_stats(ctypes.Structure):

@@ -29,6 +29,7 @@ extern "C" void bms_default_opts(bms_opts* o) {
   o->max_refine = 4;
   o->qr_passes = 1;
   o->use_graph = 1;
+  o->mixed_switch = 3e-4;
 }
 
 extern "C" const char* bms_error_string(int s) {

@@ -51,6 +51,8 @@ enum Slot {
   S_COLS,  // per-column scale factors
   S_RBC,   // one column of S_RB
   S_EC,    // its correction
+  S_E2,    // FP64 solutions of the FP32 multi-shift phase
+  S_CMAT,  // n x n FP64 coefficient matrix
   S_COUNT
 };
 
@@ -475,9 +477,184 @@ static int validate_solve(bms_ctx* c, double mass, int n, int ns, const double* 
       return set_err(c, BMS_EINVAL, "opts.qr_passes must be 1 or 2");
     if (o->precision == BMS_PREC_MIXED && o->reliable_interval < 1)
       return set_err(c, BMS_EINVAL, "opts.reliable_interval must be >= 1");
+    if (!(o->mixed_switch == o->mixed_switch))
+      return set_err(c, BMS_EINVAL, "opts.mixed_switch must be a number");
     if (o->max_refine < 0) return set_err(c, BMS_EINVAL, "opts.max_refine must be >= 0");
   }
   if (!c->gauge_set) return set_err(c, BMS_ESTATE, "no gauge field set");
+  return BMS_OK;
+}
+
+// x = G^-1 b for Hermitian positive definite G (n x n, row-major) and n
+// right-hand sides b (columns of the n x n matrix B): Cholesky on the host.
+// Fails (false) when a pivot falls below 1e-12 of G's largest diagonal entry.
+static bool host_hpd_solve(int n, std::vector<double2>& G, std::vector<double2>& Bm) {
+  std::vector<double2> L((size_t)n * n, make_double2(0, 0));
+  double gmax = 0;
+  for (int j = 0; j < n; ++j) gmax = std::max(gmax, G[j * n + j].x);
+  auto mul = [](double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
+  auto cjm = [](double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); };
+  for (int j = 0; j < n; ++j) {
+    double d = G[j * n + j].x;
+    for (int k = 0; k < j; ++k) d -= L[j * n + k].x * L[j * n + k].x + L[j * n + k].y * L[j * n + k].y;
+    if (!(d > 1e-12 * gmax)) return false;
+    d = std::sqrt(d);
+    L[j * n + j] = make_double2(d, 0);
+    for (int i = j + 1; i < n; ++i) {
+      double2 v = G[i * n + j];
+      for (int k = 0; k < j; ++k) {
+        double2 t = cjm(L[j * n + k], L[i * n + k]);  // L_ik conj(L_jk)
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      L[i * n + j] = make_double2(v.x / d, v.y / d);
+    }
+  }
+  for (int c = 0; c < n; ++c) {  // L L^H x = b, column c
+    std::vector<double2> y(n);
+    for (int i = 0; i < n; ++i) {
+      double2 v = Bm[i * n + c];
+      for (int k = 0; k < i; ++k) {
+        double2 t = mul(L[i * n + k], y[k]);
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      y[i] = make_double2(v.x / L[i * n + i].x, v.y / L[i * n + i].x);
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double2 v = y[i];
+      for (int k = i + 1; k < n; ++k) {
+        double2 t = cjm(L[k * n + i], Bm[k * n + c]);  // conj(L_ki) x_k
+        v.x -= t.x;
+        v.y -= t.y;
+      }
+      Bm[i * n + c] = make_double2(v.x / L[i * n + i].x, v.y / L[i * n + i].x);
+    }
+  }
+  return true;
+}
+
+// The FP32 phase of the mixed solver. After the FP64 block multi-shift phase
+// has brought the smallest shift to the switch residual, every shift that is
+// still updated shares its residual block up to a right factor: R_s = R_0 C_s
+// (R_s = Q delta^(s) with one Q for all shifts). One FP32 block multi-shift
+// solve of (A + sigma_s) E_s = R' for the column-normalised R' = R_0 D^-1 then
+// corrects all of them: X_s += E_s C'_s with C'_s = (R'^H R')^-1 R'^H R_s, the
+// least-squares right factor (exact up to the FP64 phase's rounding). Shifts
+// already converged are left to the per-shift defect correction. In FP32 a
+// shifted solution drifts from its recurrence by about eps_32 times its
+// condition number times the residual it starts from, which is why the FP64
+// phase runs first: started from the switch residual, that drift stays near
+// the target. Returns BMS_OK without changing X when it does not apply.
+static int mixed_phase2(bms_ctx* c, double mass, int n, int ns, const double* shifts,
+                        const int* order, double tol, int max_iter, const bms_opts& o,
+                        const void* B, void* X, int& iters, int& reliable) {
+  int rc;
+  std::vector<double> rn2, bn2;
+  if ((rc = residual_norms(c, mass, n, ns, shifts, B, X, rn2, bn2))) return rc;
+  auto worst = [&](int s) {
+    double m = 0;
+    for (int i = 0; i < n; ++i) m = std::max(m, std::sqrt(rn2[s * n + i] / bn2[i]));
+    return m;
+  };
+  const int s0 = order[0];
+  if (!(worst(s0) > tol) || !(worst(s0) < 1.0)) return BMS_OK;
+  // the shifts still updated by the FP64 phase (their residuals are well above
+  // tol; frozen ones sit near tol and go to the defect correction)
+  std::vector<int> act;
+  double wmax = 0;
+  for (int k = 0; k < ns; ++k) {
+    int s = order[k];
+    if (k == 0 || worst(s) > 10.0 * tol) {
+      act.push_back(s);
+      wmax = std::max(wmax, worst(s));
+    }
+  }
+  const int na = (int)act.size();
+  int rows = 3 * c->vh;
+  size_t blk = (size_t)rows * n;
+  void *RB, *E, *E2, *cols, *t1, *t2, *res, *pp, *cm;
+  if ((rc = scratch_buf(c, S_RB, blk * sizeof(double2), &RB))) return rc;
+  if ((rc = scratch_buf(c, S_E, blk * sizeof(double2), &E))) return rc;
+  if ((rc = scratch_buf(c, S_COLS, 3 * n * sizeof(double) + 64, &cols))) return rc;
+  if ((rc = scratch_buf(c, S_R1, blk * sizeof(double2), &t1))) return rc;
+  if ((rc = scratch_buf(c, S_R2, blk * sizeof(double2), &t2))) return rc;
+  if ((rc = scratch_buf(c, S_RES, (size_t)2 * n * n * sizeof(double2) + 64, &res))) return rc;
+  if ((rc = scratch_buf(c, S_CMAT, (size_t)n * n * sizeof(double2) + 64, &cm))) return rc;
+  int nb = gram_blocks(rows, n, c->num_cu);
+  if ((rc = scratch_buf(c, S_PART, part_bytes(nb, 4 * n * n), &pp))) return rc;
+  // R' = (B - (A + s0) X_0) D^-1, D = diag |r_i| (B's column where r_i = 0)
+  std::vector<double> h(3 * n);
+  for (int i = 0; i < n; ++i) {
+    double rn = std::sqrt(rn2[s0 * n + i]), bn = std::sqrt(bn2[i]);
+    h[i] = rn > 0 ? 1.0 / rn : 0.0;
+    h[n + i] = bn > 0 ? 1.0 / bn : 1.0;
+    h[2 * n + i] = rn;
+  }
+  HIP_TRY(c, hipMemcpyAsync(cols, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  auto apply_a = [&](int s) -> int {
+    const double2* xs = (const double2*)X + (size_t)s * blk;
+    HIP_TRY(c, launch_hop<double>(c, 1, n, xs, t1, nullptr, 0.0, 1.0, nullptr));
+    HIP_TRY(c, launch_hop<double>(c, 0, n, t1, t2, xs, mass * mass + shifts[s], -1.0, nullptr));
+    return BMS_OK;
+  };
+  if ((rc = apply_a(s0))) return rc;
+  HIP_TRY(c, launch_resid_block(c->stream, rows, n, B, t2, (const double*)cols,
+                                (const double*)cols + n, RB, nullptr));
+  // C'_s from the Grams R'^H R' and R'^H R_s
+  std::vector<double2> G00((size_t)n * n), G0s((size_t)n * n);
+  HIP_TRY(c, launch_gram<double>(c->stream, rows, n, RB, RB, (double2*)res, (double2*)pp, nb,
+                                 nullptr));
+  HIP_TRY(c, hipMemcpyAsync(G00.data(), res, G00.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<std::vector<double2>> C(na);
+  for (int a = 0; a < na; ++a) {
+    const int s = act[a];
+    if ((rc = apply_a(s))) return rc;
+    HIP_TRY(c, launch_resid_block(c->stream, rows, n, B, t2, nullptr, nullptr, E, nullptr));
+    HIP_TRY(c, launch_gram<double>(c->stream, rows, n, RB, E, (double2*)res, (double2*)pp, nb,
+                                   nullptr));
+    HIP_TRY(c, hipMemcpyAsync(G0s.data(), res, G0s.size() * sizeof(double2),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<double2> G = G00;
+    if (!host_hpd_solve(n, G, G0s)) return BMS_OK;  // R' rank-deficient: leave it to refinement
+    C[a] = G0s;
+  }
+  // one FP32 multi-shift solve on R' for all of them (ascending shifts)
+  std::vector<double> sig(na);
+  std::vector<int> xm(na);
+  for (int a = 0; a < na; ++a) {
+    sig[a] = shifts[act[a]];
+    xm[a] = a;
+  }
+  if ((rc = scratch_buf(c, S_E2, (size_t)na * blk * sizeof(double2), &E2))) return rc;
+  double t2tol = std::min(0.5, std::max(0.5 * tol / wmax, 1e-13));
+  bms_opts o2 = o;
+  o2.freeze_tol = 0.0;
+  CoreResult cr;
+  if ((rc = solve_core<float>(c, mass, n, na, sig.data(), xm.data(), t2tol, max_iter, o2, RB, E2,
+                              cr)))
+    return rc;
+  iters += cr.iters;
+  reliable += cr.reliable;
+  // a failed, diverged or softly stopped (breakdown, non-finite values) FP32
+  // phase gives no usable correction: X stays as the FP64 phase left it
+  if (cr.error || cr.diverged || cr.soft) return BMS_OK;
+  std::vector<double> ones(n, 1.0);
+  HIP_TRY(c, hipMemcpyAsync(cols, ones.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  for (int a = 0; a < na; ++a) {
+    HIP_TRY(c, hipMemcpyAsync(cm, C[a].data(), (size_t)n * n * sizeof(double2),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_block_matmul_d<double>(c->stream, rows, n, (const double2*)E2 + a * blk,
+                                             (const double2*)cm, E, nullptr));
+    HIP_TRY(c, launch_axpy_cols(c->stream, rows, n, (double2*)X + (size_t)act[a] * blk, E,
+                                (const double*)cols));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return BMS_OK;
 }
 
@@ -492,9 +669,25 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
   std::vector<double> sig(ns);
   for (int s = 0; s < ns; ++s) sig[s] = shifts[order[s]];
   CoreResult cr;
-  if ((rc = solve_core<T>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X, cr)))
+  int refine_iters = 0, reliable = 0;
+  // MIXED: an FP64 block multi-shift phase down to the switch residual (every
+  // shift kept updated until the final tolerance), then the FP32 phase
+  const bool two_phase = sizeof(T) == 4 && o.mixed_switch > tol && o.mixed_switch < 1.0;
+  if (two_phase) {
+    bms_opts o1 = o;
+    o1.freeze_tol = o.freeze_tol > 0 ? std::min(o.freeze_tol, 0.5 * tol) : 0.5 * tol;
+    if ((rc = solve_core<double>(c, mass, n, ns, sig.data(), order.data(), o.mixed_switch,
+                                 max_iter, o1, B, X, cr)))
+      return rc;
+    if (!cr.error &&
+        (rc = mixed_phase2(c, mass, n, ns, shifts, order.data(), tol, max_iter, o, B, X,
+                           refine_iters, reliable)))
+      return rc;
+  } else if ((rc = solve_core<T>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X,
+                                 cr))) {
     return rc;
-  int refine_iters = 0, reliable = cr.reliable;
+  }
+  reliable += cr.reliable;
   bool fell_back = false;
   if (sizeof(T) == 4 && cr.diverged) {
     // the FP32 iteration diverged or stalled: solve all shifts again in FP64

@@ -26,7 +26,11 @@ def _ctx(torch, dims, U):
     return c
 
 
-def test_mixed_parity_8x8x8x8(torch):
+# mixed_switch 3e-4 (the default): FP64 multi-shift phase to 3e-4, then one
+# FP32 multi-shift phase on the remaining residual; 1e-7: a short FP32 phase;
+# 0: FP32 from the start with per-shift defect correction
+@pytest.mark.parametrize("switch", [3e-4, 1e-7, 0.0])
+def test_mixed_parity_8x8x8x8(torch, switch):
     from paper_1808_01829_amd import bms
     w = configs.WORKLOADS["c2"]
     r = configs.workload_coefficients("c2")
@@ -35,11 +39,14 @@ def test_mixed_parity_8x8x8x8(torch):
     B = gaussian_block(dims, n, 2001)
     c = _ctx(torch, dims, U)
     X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-11, precision=bms.BMS_PREC_MIXED,
-                    reliable_interval=50)
+                    reliable_interval=50, mixed_switch=switch)
     X = to_np(X)
     tr = O.true_residuals(dims, BC, U, m, r.beta, B, X)
     assert tr.max() <= 1e-11
-    assert st["reliable_updates"] > 0
+    if switch == 0.0:
+        assert st["reliable_updates"] > 0
+    else:
+        assert st["refine_iterations"] > 0  # the FP32 phase ran
     Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-13)
     kap = (16 + m * m + r.beta) / (m * m + r.beta)
     for s in range(len(r.beta)):
