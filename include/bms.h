@@ -231,8 +231,11 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  * 5 = the matrix-core kernel with rows staged through LDS, 1, 2 or 4 chunks
  * in flight per work-group; 0 = the vector kernel; -1 = the default (2).
  * For BMS_KERNEL_HOP: 1 = four threads per site sharing the site's links
- * (n = 4, 8, 16, 32), 0 = one thread per site and column group, -1 = the
- * default (1 where it applies, except FP32 at n = 16). Other kernels are rejected with BMS_EINVAL;
+ * (n = 4, 8, 16, 32), 0 = one thread per site and column group, 2 and 3 = 0
+ * and 1 in a tiled traversal (8 x 8 x 4 tiles in y, z, t of whole x-rows,
+ * each (y, z) pencil on one XCD; lattices the tiles do not fit run in the
+ * natural order), -1 = the default (1 where it applies, tiled in FP64 at
+ * n >= 16). Other kernels are rejected with BMS_EINVAL;
  * other widths and precisions ignore the setting. Results do not depend on the variant beyond rounding
  * order.
  */

@@ -1,3 +1,4 @@
+#include <cstring>
 // Gauge import and the multi-RHS staggered half hop (the block Dirac operator
 // of Sec. III-IV: one application serves all n pseudofermion columns).
 #include "internal.h"
@@ -53,6 +54,39 @@ __global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restri
   }
 }
 
+// Tiled traversal. A tile is hx x ty x tz x tt checkerboard sites (whole
+// x-rows); the tiles of one (y, z) pencil are walked along t. Work-groups go
+// to the 8 XCDs in turn (work-group b to XCD b % 8); XCD x takes pencils x,
+// x + 8, ... and runs its work-groups tile after tile, so a tile's
+// t-neighbour slices were just read by the previous tile on the same XCD and
+// only the y and z faces come from beyond that XCD's L2.
+struct HopTiles {
+  int on;            // 0: natural order (the kernels then ignore the plan)
+  int ty, tz, tt;    // tile extent in y, z, t
+  int npy;           // pencils along y (Ly / ty)
+  int tpp;           // tiles per pencil (Lt / tt)
+  int bpt;           // work-groups per tile
+  int spb;           // sites per work-group
+};
+
+// first checkerboard site of this work-group's sites
+__device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom& g) {
+  const uint32_t b = blockIdx.x;
+  const uint32_t x = b & 7, j = b >> 3;
+  const uint32_t per_pencil = (uint32_t)(m.bpt * m.tpp);
+  const uint32_t pencil = x + 8u * (j / per_pencil);
+  const uint32_t jt = j % per_pencil;
+  const uint32_t tile_t = jt / (uint32_t)m.bpt, bit = jt % (uint32_t)m.bpt;
+  const uint32_t py = pencil % (uint32_t)m.npy, pz = pencil / (uint32_t)m.npy;
+  // local index of the first site inside the tile (x-rows of hx sites, then y, z, t)
+  const uint32_t li = bit * (uint32_t)m.spb;
+  const uint32_t r = li / (uint32_t)g.hx;  // whole rows: spb is a multiple of hx
+  const uint32_t yl = r % (uint32_t)m.ty, r2 = r / (uint32_t)m.ty;
+  const uint32_t zl = r2 % (uint32_t)m.tz, tl = r2 / (uint32_t)m.tz;
+  const uint32_t y = py * m.ty + yl, z = pz * m.tz + zl, t = tile_t * m.tt + tl;
+  return (uint32_t)g.hx * (y + (uint32_t)g.L[1] * (z + (uint32_t)g.L[2] * t));
+}
+
 // out(s) = b * sum_k L_k(s) in(nbr_k(s)) + a * aux(s) on n columns.
 // One thread per (site, column group g): the n/R threads of a site share its
 // links (the block operator reads each link once per n columns) and each link
@@ -68,16 +102,25 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
                                                 cplx<T>* __restrict__ out,
                                                 const cplx<T>* __restrict__ aux, T a, T b, Geom g,
                                                 int n, FastDiv dgrp, int par, int sbl,
-                                                const int* __restrict__ skip) {
+                                                const int* __restrict__ skip, HopTiles tiles) {
   using C = cplx<T>;
   if (skip && *skip) return;
   const uint32_t ngrp = dgrp.d;  // n / R column groups per site
   uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
   if (tid >= (uint32_t)g.vh * ngrp) return;
-  uint32_t s = fdiv(tid, dgrp);
+  uint32_t s, grp;
+  if (tiles.on) {
+    // BMS_WG / ngrp consecutive sites (whole x-rows) of a tile
+    const uint32_t ls = fdiv(threadIdx.x, dgrp);
+    s = hop_first_site(tiles, g) + ls;
+    grp = threadIdx.x - ls * ngrp;
+  } else {
+    s = fdiv(tid, dgrp);
+    grp = tid - s * ngrp;
+  }
   constexpr bool kInterleave = sizeof(T) == 8;
   const int cstep = kInterleave ? (int)ngrp : 1;  // column stride of a thread
-  const int j0 = (int)(tid - s * ngrp) * (kInterleave ? 1 : R);  // its first column
+  const int j0 = (int)grp * (kInterleave ? 1 : R);  // its first column
   SiteCoord c = site_coords(s, g, par);
   C acc[3][R];
 #pragma unroll
@@ -91,19 +134,21 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
     int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
     const C* src = in + (size_t)nb * 3 * n + j0;
     const C* L = links + link_off(s, k, 0, sbl);
-    C l[9];
+    C l[9], v[3][R];
 #pragma unroll
     for (int e = 0; e < 9; ++e) l[e] = L[e * st];
 #pragma unroll
-    for (int cb = 0; cb < 3; ++cb) {
-      C v[R];
+    for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = src[cb * n + r * cstep];
+      for (int r = 0; r < R; ++r) v[cb][r] = src[cb * n + r * cstep];
+    // all of the hop's loads in flight before the first use (as in k_hop_q)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
       for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[r], acc[a3][r]);
-    }
+        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[cb][r], acc[a3][r]);
   }
   size_t o = (size_t)s * 3 * n + j0;
 #pragma unroll
@@ -142,14 +187,14 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
                                                   cplx<T>* __restrict__ out,
                                                   const cplx<T>* __restrict__ aux, T a, T b,
                                                   Geom g, int n, int par, int sbl,
-                                                  const int* __restrict__ skip) {
+                                                  const int* __restrict__ skip, HopTiles tiles) {
   using C = cplx<T>;
   if (skip && *skip) return;
-  const uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
   // whole quads leave together (4 * Vh threads), so every DPP source lane is active
-  if (tid >= (uint32_t)g.vh * 4) return;
-  const uint32_t s = tid >> 2;
-  const int q = (int)(tid & 3);
+  if (blockIdx.x * BMS_WG + threadIdx.x >= (uint32_t)g.vh * 4) return;
+  const uint32_t s = tiles.on ? hop_first_site(tiles, g) + (threadIdx.x >> 2)
+                              : (blockIdx.x * BMS_WG + threadIdx.x) >> 2;
+  const int q = (int)(threadIdx.x & 3);
   constexpr bool kInterleave = sizeof(T) == 8;
   const int cstep = kInterleave ? 4 : 1;
   const int j0 = kInterleave ? q : q * R;
@@ -161,6 +206,9 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
   const size_t st = (size_t)1 << sbl;
+  // Per hop every load (three link elements, 3R input columns) is issued
+  // before any of them is used; the scheduling barrier keeps the scheduler
+  // from spreading them next to their uses, which leaves about two in flight.
 #pragma unroll 2
   for (int k = 0; k < 8; ++k) {
     const int mu = k & 3;
@@ -168,6 +216,12 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
     const C* src = in + (size_t)nb * 3 * n + j0;
     const C* L = links + link_off(s, k, 0, sbl);
     const C t0 = L[q * st], t1 = L[(q + 4) * st], t2 = L[e2 * st];
+    C v[3][R];
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[cb][r] = src[cb * n + r * cstep];
+    __builtin_amdgcn_sched_barrier(0);
     C l[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
@@ -180,15 +234,11 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
       }
     }
 #pragma unroll
-    for (int cb = 0; cb < 3; ++cb) {
-      C v[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = src[cb * n + r * cstep];
+    for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
       for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[r], acc[a3][r]);
-    }
+        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[cb][r], acc[a3][r]);
   }
   const size_t o = (size_t)s * 3 * n + j0;
 #pragma unroll
@@ -211,29 +261,55 @@ hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void*
   return hipGetLastError();
 }
 
+// The tile plan for spb sites per work-group (off when the lattice does not
+// divide into whole-row tiles whose (y, z) pencils split evenly over 8 XCDs).
+static HopTiles hop_tiles(const bms_ctx* c, int spb, int ty, int tz, int tt) {
+  HopTiles m;
+  memset(&m, 0, sizeof m);
+  const Geom& g = c->geom;
+  if (spb % g.hx || ty % (spb / g.hx) || g.L[1] % ty || g.L[2] % tz || g.L[3] % tt) return m;
+  const long tile = (long)g.hx * ty * tz * tt;
+  const int np = (g.L[1] / ty) * (g.L[2] / tz);
+  if (tile % spb || np % 8) return m;
+  m.on = 1;
+  m.ty = ty;
+  m.tz = tz;
+  m.tt = tt;
+  m.npy = g.L[1] / ty;
+  m.tpp = g.L[3] / tt;
+  m.bpt = (int)(tile / spb);
+  m.spb = spb;
+  return m;
+}
+
 template <typename T>
 hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
                       double a, double b, const int* skip) {
   const DevBuf& lb = sizeof(T) == 8 ? c->links64 : c->links32;
   size_t pstride = (size_t)c->nblk * 72 << c->sbl;
   const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
-  // four threads per site sharing the links, for n = 4, 8, 16, 32; by default
-  // not for FP32 at n = 16, where the consecutive-column kernel measured faster
-  const bool quad_default = !(sizeof(T) == 4 && n == 16);
-  // At most `cap` resident blocks per compute unit, by reserving LDS the
+  // Variants: 0 one thread per (site, column group), 1 four threads per site
+  // sharing the links (n = 4, 8, 16, 32), 2 and 3 the same in the tiled
+  // traversal; the default is 1, tiled in FP64 at n >= 16. Measured at 32^4,
+  // one half hop: FP64 n = 16 415 us (tiled) / 453 (natural), FP32 n = 16 246,
+  // FP64 n = 8 259, FP32 n = 8 162 (quad kernel).
+  const int hv = c->hop_variant;
+  const bool quad_ok = n == 4 || n == 8 || n == 16 || n == 32;
+  const bool quad = quad_ok && (hv == 1 || hv == 3 || hv < 0);
+  const bool tiled = hv == 2 || hv == 3 || (hv < 0 && sizeof(T) == 8 && n >= 16);
+  // At most `cap` resident work-groups per compute unit, by reserving LDS the
   // kernel does not use: fewer sites in flight keep the neighbours' re-reads
-  // inside each XCD's L2 (measured at 32^4: FP64 n = 16 513 -> 455 us with
-  // two blocks, FP32 n = 16 276 -> 268 us with four, FP32 n = 8 174 -> 169
-  // us with two; other widths unchanged).
-  const int cap = sizeof(T) == 8 ? (n >= 16 ? 2 : 0) : (n == 16 ? 4 : (n == 8 ? 2 : 0));
+  // inside each XCD's L2 (at 32^4 FP64 n = 16 513 -> 455 us natural order).
+  const int cap = n >= 16 ? 2 : (n == 8 ? 3 : 0);
   const size_t lds = cap > 0 && c->lds_per_cu > 0 ? (size_t)c->lds_per_cu / (cap + 1) + 1 : 0;
-  if ((c->hop_variant == 1 || (c->hop_variant < 0 && quad_default)) &&
-      (n == 4 || n == 8 || n == 16 || n == 32)) {
+  constexpr int kTy = 8, kTz = 8, kTt = 4;  // tile extent in y, z, t
+  if (quad) {
     dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);
+    HopTiles tiles = tiled ? hop_tiles(c, BMS_WG / 4, kTy, kTz, kTt) : HopTiles{};
 #define HOPQ(RR)                                                                           \
   k_hop_q<T, RR><<<qgrid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out, \
                                                  (const cplx<T>*)aux, (T)a, (T)b, c->geom, \
-                                                 n, par, c->sbl, skip)
+                                                 n, par, c->sbl, skip, tiles)
     switch (n) {
       case 4: HOPQ(1); break;
       case 8: HOPQ(2); break;
@@ -248,10 +324,12 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   uint32_t nthr = (uint32_t)c->vh * ngrp;
   dim3 grid((nthr + BMS_WG - 1) / BMS_WG);
   FastDiv dg = make_fastdiv(ngrp);
+  HopTiles tiles = tiled && BMS_WG % ngrp == 0 ? hop_tiles(c, BMS_WG / (int)ngrp, kTy, kTz, kTt)
+                                               : HopTiles{};
 #define HOP_LAUNCH(RR)                                                                     \
   k_hop<T, RR><<<grid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out,    \
                                               (const cplx<T>*)aux, (T)a, (T)b, c->geom, n, \
-                                              dg, par, c->sbl, skip)
+                                              dg, par, c->sbl, skip, tiles)
   if (R == 4)
     HOP_LAUNCH(4);
   else if (R == 2)

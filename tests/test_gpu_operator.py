@@ -100,3 +100,30 @@ def test_errors(torch):
     with pytest.raises(bms.BmsError) as e:
         bms.bms_apply_hop(c.h, 2, 2, v, torch.empty_like(v))
     assert e.value.code == bms.BMS_EINVAL
+
+
+@pytest.mark.parametrize("n", [16, 8])
+def test_hop_tiled_traversal(torch, n):
+    # 16x16x32x4: the smallest lattice the 8x8x4-tile plan accepts (8 rows of
+    # 8 checkerboard sites per work-group, (16/8)*(32/8) = 8 pencils, one per
+    # XCD); every variant, natural and tiled, against the oracle
+    from paper_1808_01829_amd import bms
+    dims, bc = (16, 16, 32, 4), (1, 1, 1, -1)
+    U = random_gauge(dims, 0.7, 105)
+    c = _ctx(dims, bc, U)
+    v = gaussian_block(dims, n, 106)
+    aux = gaussian_block(dims, n, 107)
+    for par in (0, 1):
+        ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], axis=-1)
+        for variant in (-1, 0, 1, 2, 3):
+            c.set_variant(bms.BMS_KERNEL_HOP, variant)
+            out = to_np(c.apply_hop(par, to_dev(torch, v)))
+            assert rel(out, ref) < 1e-13, (par, variant)
+            out32 = to_np(c.apply_hop(par, to_dev(torch, v.astype(np.complex64)), bms.BMS_PREC_F32))
+            assert rel(out32, ref) < 2e-6, (par, variant)
+    # the D_eo half hop with its aux term (M^dag M) through the tiled FP64 default
+    for variant in (-1, 0, 3):
+        c.set_variant(bms.BMS_KERNEL_HOP, variant)
+        ref = O.mdagm(dims, bc, U, 0.05, 0.3, v)
+        out = to_np(c.apply_mdagm(0.05, 0.3, to_dev(torch, v)))
+        assert rel(out, ref) < 1e-13, variant
