@@ -96,6 +96,12 @@ def test_calls_without_gauge_fail_on_the_host(lib):
         o.qr_passes = 3
         assert lib.bms_solve(ctx, 0.1, 1, 2, sh, 1e-8, 100, ctypes.byref(o), dummy, other,
                              None) == bms.BMS_EINVAL
+        lib.bms_default_opts(ctypes.byref(o))
+        assert o.mixed_switch == 3e-4
+        o.mixed_switch = float("nan")
+        assert lib.bms_solve(ctx, 0.1, 1, 2, sh, 1e-8, 100, ctypes.byref(o), dummy, other,
+                             None) == bms.BMS_EINVAL
+        assert "mixed_switch" in lib.bms_last_error(ctx).decode()
         assert lib.bms_force(ctx, 1, 2, sh, dummy, other, 7) == bms.BMS_EINVAL
         assert lib.bms_set_gauge(ctx, None) == bms.BMS_EINVAL
         assert lib.bms_set_variant(ctx, bms.BMS_KERNEL_UPDATE, 9) == bms.BMS_EINVAL
