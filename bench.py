@@ -37,12 +37,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s):
+def set_omp_threads(k):
+    """Thread count of the oracle's OpenMP regions from here on (None: unchanged)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+        return True
+    except OSError:
+        return False
+
+
+def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s, threads=None):
     """Time the oracle's multi-shift CG (one column, all shifts) per iteration
     by differencing two bounded runs, then scale to a full solve."""
     import numpy as np
 
     from oracle import oracle as O
+    if threads is not None and not set_omp_threads(threads):
+        raise RuntimeError("cannot set the OpenMP thread count")
     dims, bc, m = w["dims"], (1, 1, 1, -1), w["mass"]
     sh = np.sort(r.beta)
     b = np.ascontiguousarray(B[..., 0])
@@ -56,7 +68,8 @@ def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s):
     t2 = time.time() - t0
     per_it = max((t2 - t1) / (n2 - 1), 1e-9)
     solve_s = per_it * per_vector_iters
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=1.0 / solve_s, unit="RHS-solves/s", cores=threads, kind="oracle",
                 sample=("oracle C FP64 multi-shift CG, 1 column x %d shifts at %s: %d vs 1 "
                         "iterations timed (%.1f s), %.3f s/iteration, scaled to the %d "
@@ -141,6 +154,43 @@ def per_vector(ctx, bms, m, r, Bd, tol, cols, torch):
     return iters, cols / (time.perf_counter() - t0)
 
 
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def force_measure(bms, torch, np, configs, reps=3):
+    """The force kernel at the force workload (K = n_pf x N_s columns), random
+    solutions (its cost does not depend on their values): time, algorithmic
+    GB/s and FP64 TFLOP/s against both roofs."""
+    from paper_1808_01829_amd.inputs import random_gauge
+    wf = configs.WORKLOADS["c4"]
+    rf = configs.workload_coefficients("c4")
+    dims, n, ns = wf["dims"], wf["n"], rf.n_poles
+    ctx = bms.Context(dims, (1, 1, 1, -1))
+    ctx.set_gauge(torch.from_numpy(random_gauge(dims, wf["eps"], 7001)).cuda())
+    vh = int(np.prod(dims)) // 2
+    g = torch.Generator(device="cuda").manual_seed(7002)
+    X = torch.randn((ns, vh, 3, n), dtype=torch.complex128, device="cuda", generator=g)
+    alpha = list(rf.alpha)
+    ctx.force(alpha, X)  # warm-up (scratch allocation, Y buffer)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        ctx.force(alpha, X)
+    torch.cuda.synchronize()
+    ms, nl, by = ctx.timing_read()["force"]
+    ctx.timing(False)
+    us = 1e3 * ms / nl
+    vol = int(np.prod(dims))
+    flops = 4.0 * vol * n * ns * 78  # per link and column: 3 scalings, 9 conj. FMAs
+    gbs = by / nl / (us * 1e-6) / 1e9
+    tf = flops / (us * 1e-6) / 1e12
+    return dict(kernel="k_force", workload="c4: %s, n_pf=%d, %d shifts (K=%d), FP64" % (
+        "x".join(map(str, dims)), n, ns, n * ns), avg_us=round(us, 1),
+        algorithmic_bytes=round(by / nl), flops=flops, gbs=round(gbs, 1),
+        hbm_frac=round(gbs / HBM_PEAK_GBS, 4), tflops=round(tf, 2),
+        fp64_valu_frac=round(tf / FP64_VALU_PEAK_TFLOPS, 4))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +208,11 @@ def main():
                     help="skip bms_autotune (kernel variants picked on this problem before warmup)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the workload's uneven batch of lattices (reported aside)")
+    ap.add_argument("--seeds", type=int, default=3,
+                    help="gauge/RHS seeds: the timed seed plus one solve on each further seed "
+                         "(median, min, max reported aside)")
+    ap.add_argument("--no-force", action="store_true",
+                    help="skip the force-kernel measurement (reported aside)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -265,15 +320,47 @@ def main():
                      max_true_residual=ost["max_true_residual"])
         log("bench: %s: %s" % (op, other))
 
+    seeds = None
+    if args.seeds > 1:
+        vals = [value]
+        for k in range(1, args.seeds):
+            Uk = random_gauge(dims, w["eps"], 1000 * w["id"] + 10 * k)
+            Bk = gaussian_block(dims, n, 1000 * w["id"] + 10 * k + 1)
+            ctx.set_gauge(torch.from_numpy(Uk).to(dev))
+            Bkd = torch.from_numpy(Bk).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sk = ctx.solve(m, r.beta, Bkd, tol=tol, max_iter=20000, opts=opts,
+                              raise_on_error=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res = np.asarray(sk["true_residual"])
+            vals.append(int(np.sum(np.all(res <= tol, axis=0))) / dt)
+            del Bkd
+        ctx.set_gauge(Ud)
+        seeds = dict(values=[round(v, 4) for v in vals], median=round(float(np.median(vals)), 4),
+                     min=round(min(vals), 4), max=round(max(vals), 4), unit="RHS-solves/s",
+                     note="first: the timed seed (mean of the timed steps); others: one solve each")
+        log("bench: seeds %s" % (seeds,))
+
+    force = None
+    if not args.no_force:
+        force = force_measure(bms, torch, np, configs)
+        log("bench: force %s" % (force,))
+
     batch = None
     if w.get("batch") and not args.no_batch:
         batch = run_batch(args, w, r, bms, opts, torch, np)
         log("bench: batch %s" % (batch,))
 
     cpu = None
+    cpu1 = None
     if not args.no_cpu:
         try:
             cpu = cpu_oracle_sample(U, B, w, r, int(np.mean(pv_iters or iters)), args.cpu_seconds)
+            cpu1 = cpu_oracle_sample(U, B, w, r, int(np.mean(pv_iters or iters)),
+                                     args.cpu_seconds / 2, threads=1)
+            set_omp_threads(cpu["cores"])
         except Exception as e:  # the oracle is optional for the measurement
             log("bench: cpu baseline failed: %r" % (e,))
 
@@ -290,6 +377,14 @@ def main():
                     lattice=list(dims), n_pf=n, n_shifts=r.n_poles, tol=tol, precision=prec),
         roofline=roofline,
         cpu_baseline=cpu,
+        cpu_baseline_1thread=cpu1,
+        rhs_shift_solves_per_s=round(value * r.n_poles, 3),
+        dslash=dict(kernel="hop (both half hops)",
+                    gbs=round(kernels["hop"]["gbs"], 1) if "hop" in kernels else None,
+                    hbm_frac=round(kernels["hop"]["gbs"] / HBM_PEAK_GBS, 4)
+                    if "hop" in kernels else None),
+        seeds=seeds,
+        force=force,
         per_vector=dict(value=round(pv_rate, 4) if pv_rate == pv_rate else None,
                         unit="RHS-solves/s", columns=args.baseline_cols,
                         iterations=pv_iters, dtype="f64"),

@@ -206,6 +206,9 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
  *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per active
  *                       shift P^(s), X^(s) read and written
  *   BMS_KERNEL_SMALL    the n x n kernels (no block data)
+ *   BMS_KERNEL_FORCE    the force kernel of bms_force (the D_oe hops before it
+ *                       are not included): the solutions X and Y = D_oe X of
+ *                       every shift read once, the FP64 links, the output
  * bms_timing_enable(ctx, 1) also clears the
  * accumulators; bms_timing_read returns them (host pointers, any may be NULL).
  */
@@ -214,7 +217,8 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
 #define BMS_KERNEL_CHOLQR 2
 #define BMS_KERNEL_UPDATE 3
 #define BMS_KERNEL_SMALL 4
-#define BMS_NKERNELS 5
+#define BMS_KERNEL_FORCE 5
+#define BMS_NKERNELS 6
 
 int bms_timing_enable(bms_ctx* ctx, int enable);
 

@@ -37,7 +37,8 @@ BMS_KERNEL_GRAM = 1
 BMS_KERNEL_CHOLQR = 2
 BMS_KERNEL_UPDATE = 3
 BMS_KERNEL_SMALL = 4
-KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small"]
+BMS_KERNEL_FORCE = 5
+KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small", "force"]
 
 EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create", "bms_destroy",
            "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",

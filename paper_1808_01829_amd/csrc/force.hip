@@ -26,13 +26,31 @@ struct ForceArgs {
   double alpha[BMS_MAX_SHIFTS];
 };
 
-__global__ __launch_bounds__(BMS_WG) void k_force(ForceArgs a) {
+// Sum of a complex value over the LPL lanes of this lane's group (LPL a power
+// of two dividing the wave): every lane of the group ends with the total.
+__device__ __forceinline__ double2 group_sum(double2 v, int lpl) {
+  for (int off = 1; off < lpl; off <<= 1) {
+    v.x += __shfl_xor(v.x, off);
+    v.y += __shfl_xor(v.y, off);
+  }
+  return v;
+}
+
+// One group of lpl lanes per link (the 4 links of a site are neighbouring
+// groups): lane l of the group takes columns l, l + lpl, ... of every shift,
+// so the group's loads of one colour row are one contiguous run, and the 3 x 3
+// partial sums are added across the group at the end.
+__global__ __launch_bounds__(BMS_WG) void k_force(ForceArgs a, int lpl) {
   const Geom& g = a.g;
-  uint32_t vol = 2u * g.vh;
-  uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
-  if (tid >= 4u * vol) return;
-  int mu = tid / vol;
-  uint32_t idx = tid - mu * vol;
+  const uint32_t vol = 2u * g.vh;
+  const uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
+  // whole groups leave together (lpl divides BMS_WG and 4 * vol * lpl threads
+  // are launched in whole work-groups), so every lane of a shuffle is active
+  const uint32_t link = tid / (uint32_t)lpl;
+  const int lane = (int)(tid - link * (uint32_t)lpl);
+  const bool live = link < 4u * vol;
+  const int mu = (int)(link & 3);
+  const uint32_t idx = live ? link >> 2 : 0;
   uint32_t cb = idx >> 1;
   uint32_t r = fdiv(cb, g.d_hx);
   int x = (int)(idx - r * (uint32_t)g.L[0]);
@@ -63,32 +81,40 @@ __global__ __launch_bounds__(BMS_WG) void k_force(ForceArgs a) {
   double2 m[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) m[e] = make_double2(0, 0);
-  for (int s = 0; s < a.ns; ++s) {
-    const double2* cs = colv + s * blk + (size_t)nb * 3 * n;
-    const double2* rs = rowv + s * blk + (size_t)cb * 3 * n;
-    double al = a.alpha[s] * sgn;
-    for (int i = 0; i < n; ++i) {
-      double2 c0 = cscale(cs[i], al), c1 = cscale(cs[n + i], al), c2 = cscale(cs[2 * n + i], al);
-      double2 r0 = rs[i], r1 = rs[n + i], r2v = rs[2 * n + i];
-      // m[a][b] += c[a] conj(r[b])
-      m[0] = cjfma(r0, c0, m[0]);
-      m[1] = cjfma(r1, c0, m[1]);
-      m[2] = cjfma(r2v, c0, m[2]);
-      m[3] = cjfma(r0, c1, m[3]);
-      m[4] = cjfma(r1, c1, m[4]);
-      m[5] = cjfma(r2v, c1, m[5]);
-      m[6] = cjfma(r0, c2, m[6]);
-      m[7] = cjfma(r1, c2, m[7]);
-      m[8] = cjfma(r2v, c2, m[8]);
+  if (live) {
+    for (int s = 0; s < a.ns; ++s) {
+      const double2* cs = colv + s * blk + (size_t)nb * 3 * n;
+      const double2* rs = rowv + s * blk + (size_t)cb * 3 * n;
+      double al = a.alpha[s] * sgn;
+      for (int i = lane; i < n; i += lpl) {
+        double2 c0 = cscale(cs[i], al), c1 = cscale(cs[n + i], al), c2 = cscale(cs[2 * n + i], al);
+        double2 r0 = rs[i], r1 = rs[n + i], r2v = rs[2 * n + i];
+        // m[a][b] += c[a] conj(r[b])
+        m[0] = cjfma(r0, c0, m[0]);
+        m[1] = cjfma(r1, c0, m[1]);
+        m[2] = cjfma(r2v, c0, m[2]);
+        m[3] = cjfma(r0, c1, m[3]);
+        m[4] = cjfma(r1, c1, m[4]);
+        m[5] = cjfma(r2v, c1, m[5]);
+        m[6] = cjfma(r0, c2, m[6]);
+        m[7] = cjfma(r1, c2, m[7]);
+        m[8] = cjfma(r2v, c2, m[8]);
+      }
     }
   }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) m[e] = group_sum(m[e], lpl);
+  if (!live) return;
   size_t lo = ((size_t)mu * vol + idx);
   if (!a.lie) {
+    // the group's lanes share the nine entries of the output
     double2* G = a.G + lo * 9;
-    for (int aa = 0; aa < 3; ++aa)
-      for (int bb = 0; bb < 3; ++bb) G[3 * aa + bb] = cconj(m[3 * bb + aa]);
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+      if (e % lpl == lane) G[e] = cconj(m[3 * (e % 3) + e / 3]);
     return;
   }
+  if (lane != 0) return;
   // U_mu(w) from the forward link of parity par: L = (1/2) eta b U
   const double2* L = a.links + (size_t)par * a.pstride;
   double2 u[9];
@@ -147,8 +173,31 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   a.G = (double2*)out;
   a.F = (double*)out;
   for (int s = 0; s < ns; ++s) a.alpha[s] = alpha[s];
-  uint32_t nthr = 4u * (uint32_t)c->vol;
-  k_force<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(a);
+  // lanes per link: the block width rounded up to a power of two, at most 16
+  int lpl = 1;
+  while (lpl < n && lpl < 16) lpl <<= 1;
+  uint32_t nthr = 4u * (uint32_t)c->vol * (uint32_t)lpl;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (c->timing) {
+    HIP_TRY(c, hipEventCreate(&ev[0]));
+    HIP_TRY(c, hipEventCreate(&ev[1]));
+    HIP_TRY(c, hipEventRecord(ev[0], c->stream));
+  }
+  k_force<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(a, lpl);
   HIP_TRY(c, hipGetLastError());
+  if (c->timing) {
+    // algorithmic bytes: X and Y of every shift once, the 4V FP64 links, the output
+    HIP_TRY(c, hipEventRecord(ev[1], c->stream));
+    HIP_TRY(c, hipEventSynchronize(ev[1]));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    const double vol = (double)c->vol;
+    c->kt_ms[BMS_KERNEL_FORCE] += ms;
+    c->kt_launches[BMS_KERNEL_FORCE] += 1;
+    c->kt_bytes[BMS_KERNEL_FORCE] += 2.0 * ns * blk * sizeof(double2) + 4 * vol * 9 * 16 +
+                                     (a.lie ? 4 * vol * 8 * 8 : 4 * vol * 9 * 16);
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+  }
   return stream_end(c);
 }
