@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(4 * WPP * 64) void k_gram4_lds(int rows, int per_bl
 
 // resident blocks of a BMS_WG-thread kernel per compute unit (0 if unknown)
 template <typename K>
-static int lds_occupancy(K kernel) {
+static int resident_blocks(K kernel) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, BMS_WG, 0) != hipSuccess) {
     (void)hipGetLastError();
@@ -1069,7 +1069,7 @@ hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const vo
     // fit fewer blocks per compute unit than the three the grid is sized for
 #define GL(NN, DD)                                                                              \
   do {                                                                                          \
-    static const int occ = lds_occupancy(k_gram4_lds<T, NN, 1, DD>);                            \
+    static const int occ = resident_blocks(k_gram4_lds<T, NN, 1, DD>);                            \
     const int nbl = num_cu > 0 && occ > 0 ? std::min(nb, occ * num_cu) : nb;                    \
     k_gram4_lds<T, NN, 1, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w, \
                                                       partials, skip);                          \
@@ -1089,7 +1089,7 @@ hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const vo
     // steps in flight per wave: variant 1 four, 2 (and the default) eight
 #define GR_(NN, DD)                                                                              \
   do {                                                                                           \
-    static const int occ = lds_occupancy(k_gram4_mfma<T, NN, DD>);                               \
+    static const int occ = resident_blocks(k_gram4_mfma<T, NN, DD>);                               \
     const int nbl = num_cu > 0 && occ > 0 ? std::min(nb, occ * num_cu) : nb;                     \
     k_gram4_mfma<T, NN, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w,     \
                                                     partials, skip);                             \

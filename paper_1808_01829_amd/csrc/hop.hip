@@ -1,6 +1,7 @@
-#include <cstring>
 // Gauge import and the multi-RHS staggered half hop (the block Dirac operator
 // of Sec. III-IV: one application serves all n pseudofermion columns).
+#include <cstring>
+
 #include "internal.h"
 
 namespace {
