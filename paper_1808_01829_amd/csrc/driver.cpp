@@ -26,7 +26,9 @@ std::vector<int> candidates(int kernel, int n) {
   const bool quad = n == 4 || n == 8 || n == 16 || n == 32;
   const bool mf = n == 8 || n == 16;
   switch (kernel) {
-    case BMS_KERNEL_HOP: return quad ? std::vector<int>{1, 3, 0, 2} : std::vector<int>{0, 2};
+    // -1 (the built-in default) picks per precision, which one fixed variant
+    // cannot do for the mixed solver's FP64 and FP32 phases
+    case BMS_KERNEL_HOP: return quad ? std::vector<int>{-1, 1, 3, 0, 2} : std::vector<int>{-1, 0, 2};
     case BMS_KERNEL_GRAM: return mf ? std::vector<int>{2, 1, 3} : std::vector<int>{0};
     case BMS_KERNEL_UPDATE: return mf ? std::vector<int>{4, 5, 2, 0} : std::vector<int>{2};
     default: return {};
