@@ -710,7 +710,7 @@ struct GramRaw {
 // before its slot is refilled, and every load is unconditional, so the wait
 // for a step covers only that step's loads.
 template <typename T, int N, int D>
-__global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
+__global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows,
                                                        const cplx<T>* __restrict__ P,
                                                        const cplx<T>* __restrict__ Q,
                                                        const cplx<T>* __restrict__ W,
@@ -740,7 +740,6 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows, int per_block,
   // stretch of each block vector, as a streaming copy does; each wave runs a
   // whole number of D-step rounds (no exit inside a round, whose loads would
   // then differ by path), steps past the end are empty
-  (void)per_block;
   const int nsteps = (rows + 3) >> 2;
   const int nwaves = gridDim.x * 4, vw = blockIdx.x * 4 + wave;
   const int mine = vw < nsteps ? (nsteps - vw + nwaves - 1) / nwaves : 0;
@@ -871,16 +870,14 @@ __device__ __forceinline__ void gram_operand(const cplx<T>* blk, int rl, int c,
 }
 
 // one chunk of one wave's product: all its steps' operands, then the MFMAs
-// (with WPP waves per product, wave h of the product takes steps h, h+WPP, ...)
-template <typename T, int N, bool SYM, int WPP>
+template <typename T, int N, bool SYM>
 __device__ __forceinline__ void gram_chunk(const cplx<T>* xs, const cplx<T>* ys, int g, int c,
-                                           int h,
                                            gdx4 (&acc)[GramRow<T, N>::NT][GramRow<T, N>::NT]) {
-  constexpr int NT = GramRow<T, N>::NT, ST = GCH / 4 / WPP;
+  constexpr int NT = GramRow<T, N>::NT, ST = GCH / 4;
   double x[ST][NT], y[ST][NT];
 #pragma unroll
   for (int st = 0; st < ST; ++st) {
-    const int rl = 4 * (st * WPP + h) + g;
+    const int rl = 4 * st + g;
     gram_operand<T, N>(xs, rl, c, x[st]);
     if constexpr (!SYM) gram_operand<T, N>(ys, rl, c, y[st]);
   }
@@ -902,13 +899,13 @@ __device__ __forceinline__ void gram_chunk(const cplx<T>* xs, const cplx<T>* ys,
 // multiple of D with such empty chunks): with loads skipped on some paths the
 // compiler can no longer tell which slot is still in flight and waits for all
 // of them before every fetch, which serialises the ring.
-template <typename T, int N, bool SYM, int WPP, int D>
+template <typename T, int N, bool SYM, int D>
 __device__ __forceinline__ void gram_sweep(const cplx<T>* P, const cplx<T>* Q, const cplx<T>* W,
-                                           RowRange rr, cplx<T>* stage, int xb, int yb, int h,
+                                           RowRange rr, cplx<T>* stage, int xb, int yb,
                                            gdx4 (&acc)[GramRow<T, N>::NT][GramRow<T, N>::NT]) {
   using C_ = cplx<T>;
   using GS = GramStage<T, N>;
-  constexpr int NTH = 4 * WPP * 64;                // threads of the block
+  constexpr int NTH = BMS_WG;                      // threads of the block
   constexpr int PER_T = GCH * N / NTH;             // complex per thread and staged block
   static_assert(PER_T >= 1 && GCH * N % NTH == 0, "chunk must cover the block");
   const int tid = threadIdx.x, lane = tid & 63;
@@ -959,26 +956,25 @@ __device__ __forceinline__ void gram_sweep(const cplx<T>* P, const cplx<T>* Q, c
       // keep the loads here: the scheduler would otherwise sink them next to
       // their use (the stash D - 1 chunks later), leaving no time to land
       __builtin_amdgcn_sched_barrier(0);
-      gram_chunk<T, N, SYM, WPP>(stage + ((i & 1) * 3 + xb) * GS::BS,
-                                 stage + ((i & 1) * 3 + yb) * GS::BS, g, c, h, acc);
+      gram_chunk<T, N, SYM>(stage + ((i & 1) * 3 + xb) * GS::BS,
+                            stage + ((i & 1) * 3 + yb) * GS::BS, g, c, acc);
       stash(nx[(u + 1) % D], i + 1);
       __syncthreads();
     }
   }
 }
 
-template <typename T, int N, int WPP, int D>
-__global__ __launch_bounds__(4 * WPP * 64) void k_gram4_lds(int rows, int per_block,
+template <typename T, int N, int D>
+__global__ __launch_bounds__(BMS_WG) void k_gram4_lds(int rows, int per_block,
                                                       const cplx<T>* __restrict__ P,
                                                       const cplx<T>* __restrict__ Q,
                                                       const cplx<T>* __restrict__ W,
-                                                                                                            double2* __restrict__ partials,
+                                                      double2* __restrict__ partials,
                                                       const int* __restrict__ skip) {
   using C_ = cplx<T>;
   using GR = GramRow<T, N>;
   using GS = GramStage<T, N>;
   constexpr int NR = 2 * N, NT = GR::NT, NN = N * N;
-  constexpr int NTH = 4 * WPP * 64;
   constexpr int STAGE = 2 * 3 * GS::BS * (int)sizeof(C_);
   constexpr int REDB = 4 * NR * NR * (int)sizeof(double);
   __shared__ __align__(16) unsigned char smem[STAGE > REDB ? STAGE : REDB];
@@ -986,7 +982,7 @@ __global__ __launch_bounds__(4 * WPP * 64) void k_gram4_lds(int rows, int per_bl
   C_* stage = (C_*)smem;  // [2][3][GCH][RS]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
-  const int prod = wave & 3, h = wave >> 2;  // product and, with WPP = 2, which half of it
+  const int prod = wave;  // this wave's product
   const RowRange rr = block_rows(rows, per_block);
   // this wave's product: x block and y block (0 = P, 1 = Q, 2 = W)
   const int xb = prod == 0 ? 0 : (prod == 2 ? 2 : 1);
@@ -998,33 +994,27 @@ __global__ __launch_bounds__(4 * WPP * 64) void k_gram4_lds(int rows, int per_bl
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = gdx4{0.0, 0.0, 0.0, 0.0};
   if (sym)
-    gram_sweep<T, N, true, WPP, D>(P, Q, W, rr, stage, xb, yb, h, acc);
+    gram_sweep<T, N, true, D>(P, Q, W, rr, stage, xb, yb, acc);
   else
-    gram_sweep<T, N, false, WPP, D>(P, Q, W, rr, stage, xb, yb, h, acc);
-  // each product's real Gram into LDS (tile row g + 4k, column c; with two
-  // waves per product the second adds its part after the first wrote), then
-  // the complex entries of all four products
+    gram_sweep<T, N, false, D>(P, Q, W, rr, stage, xb, yb, acc);
+  // each product's real Gram into LDS (tile row g + 4k, column c), then the
+  // complex entries of all four products
   double* R = (double*)smem + prod * NR * NR;
-  for (int half = 0; half < WPP; ++half) {
-    if (h == half) {
 #pragma unroll
-      for (int a = 0; a < NT; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-        for (int b = 0; b < NT; ++b) {
-          if (sym && b < a) continue;
+    for (int b = 0; b < NT; ++b) {
+      if (sym && b < a) continue;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            int i = a * 16 + g + 4 * k, j = b * 16 + c;
-            double v = acc[a][b][k] + (half ? R[i * NR + j] : 0.0);
-            R[i * NR + j] = v;
-            if (sym && a != b) R[j * NR + i] = v;
-          }
-        }
+      for (int k = 0; k < 4; ++k) {
+        int i = a * 16 + g + 4 * k, j = b * 16 + c;
+        R[i * NR + j] = acc[a][b][k];
+        if (sym && a != b) R[j * NR + i] = acc[a][b][k];
+      }
     }
-    __syncthreads();
-  }
+  __syncthreads();
   double2* part = partials + (size_t)blockIdx.x * 4 * NN;
-  for (int e = tid; e < 4 * NN; e += NTH) {
+  for (int e = tid; e < 4 * NN; e += BMS_WG) {
     int gi = e / NN, ij = e - gi * NN;
     int i = ij / N, j = ij - (ij / N) * N;
     part[e] = GR::entry((const double*)smem + gi * NR * NR, i, j);
@@ -1069,9 +1059,9 @@ hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const vo
     // fit fewer blocks per compute unit than the three the grid is sized for
 #define GL(NN, DD)                                                                              \
   do {                                                                                          \
-    static const int occ = resident_blocks(k_gram4_lds<T, NN, 1, DD>);                            \
+    static const int occ = resident_blocks(k_gram4_lds<T, NN, DD>);                            \
     const int nbl = num_cu > 0 && occ > 0 ? std::min(nb, occ * num_cu) : nb;                    \
-    k_gram4_lds<T, NN, 1, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w, \
+    k_gram4_lds<T, NN, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w, \
                                                       partials, skip);                          \
     grid = nbl;                                                                                 \
   } while (0)
@@ -1091,7 +1081,7 @@ hipError_t launch_gram4(hipStream_t st, int rows, int n, const void* P, const vo
   do {                                                                                           \
     static const int occ = resident_blocks(k_gram4_mfma<T, NN, DD>);                               \
     const int nbl = num_cu > 0 && occ > 0 ? std::min(nb, occ * num_cu) : nb;                     \
-    k_gram4_mfma<T, NN, DD><<<nbl, BMS_WG, 0, st>>>(rows, rows_per_block(rows, nbl), p, q, w,     \
+    k_gram4_mfma<T, NN, DD><<<nbl, BMS_WG, 0, st>>>(rows, p, q, w,                                \
                                                     partials, skip);                             \
     grid = nbl;                                                                                  \
   } while (0)
