@@ -204,7 +204,10 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
  *   BMS_KERNEL_GRAM     the iteration's four Grams: P, Q, W read
  *   BMS_KERNEL_CHOLQR   Cholesky-QR Gram: Q, W read
  *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per active
- *                       shift P^(s), X^(s) read and written
+ *                       shift P^(s), X^(s) read and written (variants 4, 5:
+ *                       per shift other than the smallest, every second
+ *                       iteration P^(s) read and written, and in the other
+ *                       two directions, X^(s) read, X^(s) and P^(s) written)
  *   BMS_KERNEL_SMALL    the n x n kernels (no block data)
  *   BMS_KERNEL_FORCE    the force kernel of bms_force (the D_oe hops before it
  *                       are not included): the solutions X and Y = D_oe X of
@@ -225,7 +228,12 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
 /*
  * Kernel variant selection. For BMS_KERNEL_UPDATE: 4 and 5 = the
  * matrix-core (MFMA) kernel at n = 8 and 16 (FP32 or FP64 blocks, the Q step
- * in FP64) with one or two 16-row tiles per wave; 0..3 = the vector kernels
+ * in FP64) with one or two 16-row tiles per wave, where the solutions of the
+ * shifts other than the smallest take two iterations' increments at once
+ * (X^(s) += P^(s)_k-1 a^(s)_k-1 + P^(s)_k a^(s)_k, two direction buffers per
+ * shift: 7 instead of 8 block vectors moved per shift every two iterations);
+ * 6 = the same kernel updating every shift every iteration, one tile per
+ * wave; 0..3 = the vector kernels
  * (0 = four row chunks per work-group with both coefficient columns in
  * registers, 1 = two chunks, one column at a time, 2 = four chunks, one
  * column at a time, 3 = two chunks, both columns); -1 restores the built-in

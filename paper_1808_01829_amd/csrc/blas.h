@@ -15,10 +15,12 @@ struct UpdateArgs {
   const double2* alpha;       // n x n FP64
   const double2* rhoinv;      // n x n FP64
   cplx<T>* P;                 // [ns][rows][n] search directions, sorted shift order
+                              // (the matrix-core update: [2][ns][rows][n], buffer pp_cur[s])
   cplx<TX>* X;                // solutions; shift s at X + xidx[s]*rows*n
   const cplx<T>* Mx;          // [ns][n][n]
   const cplx<T>* Mp;          // [ns][n][n]
-  const SolverFlags* flags;
+  const cplx<T>* Mxd;         // [ns][n][n] the deferred Mx (matrix-core update)
+  SolverFlags* flags;         // read; the matrix-core update also sets upd_done
   int xidx[BMS_MAX_SHIFTS];
 };
 
@@ -35,8 +37,13 @@ hipError_t launch_update_fast(hipStream_t st, const UpdateArgs<T, TX>& a, int va
 // update on the matrix cores (update_mfma.hip), for n = 8 and 16, with one or
 // two 16-row tiles per wave; F = double or float (the Q step is FP64 in both)
 bool update_mfma_supported(int n);
+// With SmallParams::pingpong the shifts s >= 1 follow the PP_* modes the small
+// step sets; after the last iteration launch_update_drain adds every increment
+// still pending (Q, W, alpha, rhoinv and Mp are not used there).
 template <typename F>
 hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<F, F>& a, bool two_tiles);
+template <typename F>
+hipError_t launch_update_drain(hipStream_t st, const UpdateArgs<F, F>& a);
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
                               double2* out, double2* partials, int nb);
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,
@@ -76,13 +83,14 @@ struct SmallState {
   double2* tmp;     // [n*n]     scratch
   double* rel_last; // smallest max relative true residual of sigma_0 at a reliable update
   int* counter;     // grid-completion counter of the rho kernel
-  int* nact_log;    // [max_iter] active shifts in each completed iteration
+  int* upd_log;    // [max_iter] block vectors the update of each iteration moves
 };
 
 struct SmallParams {
   int n, ns, max_iter;
   double tol, freeze_tol, breakdown_tol;
   double sigma[BMS_MAX_SHIFTS];  // sorted shifts
+  int pingpong;  // shifts s >= 1 take the two-iteration X update (matrix-core update)
 };
 
 // initial QR of B: from G = B^H B, delta_0 = chol(G)^H, out Rinv = delta_0^-1;
@@ -97,7 +105,7 @@ hipError_t launch_small_reliable(hipStream_t st, const SmallParams& p, SmallStat
                                  SolverFlags* fl, const double2* Gin, double2* Rinv_out);
 template <typename T>
 hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                             cplx<T>* Mx, cplx<T>* Mp);
+                             cplx<T>* Mx, cplx<T>* Mp, cplx<T>* Mxd);
 template <typename T>
 hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
                                      SolverFlags* fl, cplx<T>* Mp);

@@ -30,7 +30,7 @@ std::vector<int> candidates(int kernel, int n) {
     // cannot do for the mixed solver's FP64 and FP32 phases
     case BMS_KERNEL_HOP: return quad ? std::vector<int>{-1, 1, 3, 0, 2} : std::vector<int>{-1, 0, 2};
     case BMS_KERNEL_GRAM: return mf ? std::vector<int>{2, 1, 3} : std::vector<int>{0};
-    case BMS_KERNEL_UPDATE: return mf ? std::vector<int>{4, 5, 2, 0} : std::vector<int>{2};
+    case BMS_KERNEL_UPDATE: return mf ? std::vector<int>{4, 6, 5, 2, 0} : std::vector<int>{2};
     default: return {};
   }
 }

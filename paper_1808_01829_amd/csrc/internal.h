@@ -24,9 +24,25 @@ struct SolverFlags {
   int rel_restart;    // one shift: the last reliable update restarts P^(0) = Q
   int diverged;       // the true residual grew or stalled over reliable updates (soft stop)
   int rel_stall;      // reliable updates in a row without progress of the true residual
+  int upd_done;       // `iter` as seen by the last matrix-core update that ran (-1: none)
   int active[BMS_MAX_SHIFTS];  // shift still updated
   int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
   double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift
+  // Two-iteration X^(s) update of the shifts s >= 1 (matrix-core update):
+  int pp_mode[BMS_MAX_SHIFTS];  // PP_* of this iteration's update
+  int pp_cur[BMS_MAX_SHIFTS];   // P^(s) buffer (0, 1) holding the current direction
+  int pp_pend[BMS_MAX_SHIFTS];  // X^(s) still lacks P^(s) of the other buffer times Mxd^(s)
+  int pp_done[BMS_MAX_SHIFTS];  // upd_done of the last update whose mode was applied
+};
+
+// Update modes of one shift in one iteration (k = the iteration, P_k in the
+// buffer pp_cur, the other buffer holding P_{k-1} while an increment is pending):
+enum {
+  PP_NONE = 0,   // frozen, nothing pending
+  PP_NOW = 1,    // X += P_k Mx_k; P_k+1 = Q_k+1 + P_k Mp_k in place
+  PP_DEFER = 2,  // P_k+1 = Q_k+1 + P_k Mp_k into the other buffer; X waits (Mxd = Mx_k)
+  PP_FLUSH = 3,  // X += P_k-1 Mxd + P_k Mx_k; P_k+1 into the other buffer (over P_k-1)
+  PP_DRAIN = 4,  // frozen with an increment pending: X += P_k-1 Mxd
 };
 
 struct bms_ctx {

@@ -194,13 +194,18 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
     fl->error = 0;
     fl->iter = 0;
     fl->need_explicit = 0;
+    fl->upd_done = -1;
     *s.counter = 0;
   }
   if (pass == 0)
-    for (int i = threadIdx.x; i < p.ns; i += BMS_WG) {
-      fl->active[i] = 1;
+    for (int i = threadIdx.x; i < BMS_MAX_SHIFTS; i += BMS_WG) {
+      fl->active[i] = i < p.ns;
       fl->conv[i] = 0;
       fl->res[i] = 1.0;
+      fl->pp_mode[i] = PP_NONE;
+      fl->pp_cur[i] = 0;
+      fl->pp_pend[i] = 0;
+      fl->pp_done[i] = -1;
     }
   sm_load(L0, Gin, n);
   int st = sm_chol_upper(L1, L0, n, p.breakdown_tol);
@@ -313,9 +318,16 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
   }
 }
 
+// Block vectors of one shift's update in a mode (see PP_*): P and X read and
+// written, or only P, or P twice and X, ...
+__device__ __forceinline__ int pp_traffic(int mode) {
+  return mode == PP_NOW ? 4 : mode == PP_DEFER ? 2 : mode == PP_FLUSH ? 5 : mode == PP_DRAIN ? 3 : 0;
+}
+
 // Completion of one iteration's small step: count this block's arrival and
 // whether its shift met tol; the last block to arrive stops the solve when
-// all did, logs the active count and advances the iteration counter.
+// all did, logs the update's traffic (3 block vectors for the Q step plus each
+// shift's) and advances the iteration counter.
 __device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFlags* fl,
                              int done) {
   if (threadIdx.x == 0) {
@@ -324,9 +336,9 @@ __device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFl
     if ((v & 0xffff) == p.ns) {
       __threadfence();
       if ((v >> 16) == p.ns || fl->error) fl->stop = 1;
-      int na = 1;
-      for (int i = 1; i < p.ns; ++i) na += fl->active[i];
-      if (s.nact_log && fl->iter < p.max_iter) s.nact_log[fl->iter] = na;
+      int units = 3;
+      for (int i = 0; i < p.ns; ++i) units += pp_traffic(fl->pp_mode[i]);
+      if (s.upd_log && fl->iter < p.max_iter) s.upd_log[fl->iter] = units;
       fl->need_explicit = 0;
       fl->iter = fl->iter + 1;
       atomicExch(s.counter, 0);
@@ -387,6 +399,30 @@ __device__ void rho_part(const SmallParams& p, const SmallState& s, SolverFlags*
   finish_shift(p, s, fl, r < p.tol);
 }
 
+// Apply, once, what the last update that ran did to shift q's direction
+// buffers and pending increment (its mode is still in pp_mode[q]): a deferred
+// step keeps its Mx as Mxd and flips the buffer, a flush flips it and clears
+// the pending increment, a drain clears it. An update that was skipped (the
+// solve halted after this step) changed nothing and is not applied.
+template <typename C>
+__device__ void pp_commit(SolverFlags* fl, int q, const C* Mx, C* Mxd, int nn) {
+  const int u = fl->upd_done;
+  const int done = fl->pp_done[q];
+  const int m = fl->pp_mode[q];
+  __syncthreads();  // every thread has read the flags before thread 0 writes them
+  if (u == done) return;
+  if (m == PP_DEFER)
+    for (int e = threadIdx.x; e < nn; e += BMS_WG) Mxd[(size_t)q * nn + e] = Mx[(size_t)q * nn + e];
+  if (threadIdx.x == 0) {
+    if (m == PP_DEFER || m == PP_FLUSH) fl->pp_cur[q] ^= 1;
+    if (m == PP_DEFER) fl->pp_pend[q] = 1;
+    if (m == PP_FLUSH || m == PP_DRAIN) fl->pp_pend[q] = 0;
+    fl->pp_mode[q] = PP_NONE;
+    fl->pp_done[q] = u;
+  }
+  __syncthreads();  // Mx is overwritten after the copy
+}
+
 // One iteration's n x n work, after G4 = [P^H W, Q^H W, W^H W, Q^H Q]:
 //   alpha_k = (P^H W)^-1; beta^(s)_k, alpha^(s)_k (Algorithm 1, lines 10-11);
 //   V^H V from the expansion, rho_k = chol(V^H V)^H; then rho_part.
@@ -395,7 +431,7 @@ __device__ void rho_part(const SmallParams& p, const SmallState& s, SolverFlags*
 template <typename T>
 __global__ __launch_bounds__(BMS_WG) void k_small_iter(SmallParams p, SmallState s,
                                                        SolverFlags* fl, cplx<T>* Mx,
-                                                       cplx<T>* Mp) {
+                                                       cplx<T>* Mp, cplx<T>* Mxd) {
   __shared__ double2 Gk[NN], A[NN], R[NN], T0[NN], T1[NN], T2[NN], T3[NN];
   const int n = p.n, nn = n * n;
   const int q = blockIdx.x;
@@ -407,11 +443,20 @@ __global__ __launch_bounds__(BMS_WG) void k_small_iter(SmallParams p, SmallState
     return;
   }
   const int cur = fl->iter & 1, prev = cur ^ 1;
+  pp_commit(fl, q, Mx, Mxd, nn);
   if (q > 0 && (fl->conv[q] || !fl->active[q])) {
-    if (threadIdx.x == 0) fl->active[q] = 0;
+    if (threadIdx.x == 0) {
+      fl->active[q] = 0;
+      fl->pp_mode[q] = fl->pp_pend[q] ? PP_DRAIN : PP_NONE;
+    }
     finish_shift(p, s, fl, 1);
     return;
   }
+  // this iteration's update of the shift: every iteration for sigma_0 (its P
+  // feeds the operator, its X the reliable updates), else deferred and
+  // flushed in turn
+  if (threadIdx.x == 0)
+    fl->pp_mode[q] = (q == 0 || !p.pingpong) ? PP_NOW : (fl->pp_pend[q] ? PP_FLUSH : PP_DEFER);
   sm_load(Gk, s.G4, n);
   int st = sm_chol_upper(T0, Gk, n, 0.0);
   if (st) {
@@ -541,8 +586,8 @@ hipError_t launch_small_reliable(hipStream_t st, const SmallParams& p, SmallStat
 
 template <typename T>
 hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                             cplx<T>* Mx, cplx<T>* Mp) {
-  k_small_iter<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mx, Mp);
+                             cplx<T>* Mx, cplx<T>* Mp, cplx<T>* Mxd) {
+  k_small_iter<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mx, Mp, Mxd);
   return hipGetLastError();
 }
 
@@ -555,7 +600,7 @@ hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, Small
 
 #define INST_SMALL(T, C)                                                                    \
   template hipError_t launch_small_iter<T>(hipStream_t, const SmallParams&, SmallState,     \
-                                           SolverFlags*, C*, C*);                           \
+                                           SolverFlags*, C*, C*, C*);                       \
   template hipError_t launch_small_rho_explicit<T>(hipStream_t, const SmallParams&,         \
                                                    SmallState, SolverFlags*, C*);
 INST_SMALL(double, double2)

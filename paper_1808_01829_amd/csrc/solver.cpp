@@ -67,7 +67,7 @@ size_t part_bytes(int nb, int P) { return (size_t)nb * P * sizeof(double2) + 64;
 struct Work {
   int rows, n, ns;
   size_t blk;  // complex elements per block vector
-  void *W1, *W, *Q, *P, *X, *Mx, *Mp;
+  void *W1, *W, *Q, *P, *X, *Mx, *Mp, *Mxd;
   SmallState sm;
   SolverFlags* flags;
   double2* partials;
@@ -76,8 +76,15 @@ struct Work {
   int nb;
 };
 
+// The matrix-core update with the two-iteration X update of the shifts s >= 1
+// (update variants -1, 4, 5 at n = 8, 16; 6 updates every shift every iteration).
+bool use_pingpong(const bms_ctx* c, int n) {
+  const int uv = c->update_variant;
+  return update_mfma_supported(n) && (uv < 0 || uv == 4 || uv == 5);
+}
+
 template <typename T>
-int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
+int alloc_work(bms_ctx* c, int n, int ns, int max_iter, bool pingpong, Work& w) {
   int rc;
   w.n = n;
   w.ns = ns;
@@ -87,7 +94,8 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   if ((rc = scratch_buf(c, S_W1, w.blk * es, &w.W1))) return rc;
   if ((rc = scratch_buf(c, S_W, w.blk * es, &w.W))) return rc;
   if ((rc = scratch_buf(c, S_Q, w.blk * es, &w.Q))) return rc;
-  if ((rc = scratch_buf(c, S_P, w.blk * es * ns, &w.P))) return rc;
+  // two direction buffers per shift for the two-iteration update
+  if ((rc = scratch_buf(c, S_P, w.blk * es * ns * (pingpong ? 2 : 1), &w.P))) return rc;
   if ((rc = scratch_buf(c, S_X, w.blk * es * ns, &w.X))) return rc;
   size_t nn = (size_t)n * n;
   size_t small_elems = 2 * nn + 2 * nn + 8 * nn + 2 * ns * nn + 3 * nn + n + 1;
@@ -125,22 +133,43 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, Work& w) {
   if ((rc = scratch_buf(c, S_PART, part_bytes(w.nb, 4 * nn), &pp))) return rc;
   w.partials = (double2*)pp;
   void* mp;
-  if ((rc = scratch_buf(c, S_M, 2 * ns * nn * es, &mp))) return rc;
+  if ((rc = scratch_buf(c, S_M, 3 * ns * nn * es, &mp))) return rc;
   w.Mx = mp;
   w.Mp = (char*)mp + ns * nn * es;
+  w.Mxd = (char*)mp + 2 * ns * nn * es;
   void* fp;
   if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
   w.flags = (SolverFlags*)fp;
   w.sm.counter = (int*)((char*)fp + sizeof(SolverFlags));
   void* lp;
   if ((rc = scratch_buf(c, S_LOG, (size_t)max_iter * sizeof(int) + 64, &lp))) return rc;
-  w.sm.nact_log = (int*)lp;
+  w.sm.upd_log = (int*)lp;
   return BMS_OK;
 }
 
 // kernel classes of the 7 launches of one iteration (timing)
 const int kIterKernel[7] = {BMS_KERNEL_HOP,   BMS_KERNEL_HOP,   BMS_KERNEL_GRAM,  BMS_KERNEL_SMALL,
                             BMS_KERNEL_CHOLQR, BMS_KERNEL_SMALL, BMS_KERNEL_UPDATE};
+
+template <typename T>
+UpdateArgs<T, T> update_args(const Work& w) {
+  UpdateArgs<T, T> ua;
+  ua.rows = w.rows;
+  ua.n = w.n;
+  ua.ns = w.ns;
+  ua.Q = (cplx<T>*)w.Q;
+  ua.W = (const cplx<T>*)w.W;
+  ua.alpha = w.sm.alpha;
+  ua.rhoinv = w.sm.rhoinv;
+  ua.P = (cplx<T>*)w.P;
+  ua.X = (cplx<T>*)w.X;
+  ua.Mx = (const cplx<T>*)w.Mx;
+  ua.Mp = (const cplx<T>*)w.Mp;
+  ua.Mxd = (const cplx<T>*)w.Mxd;
+  ua.flags = w.flags;
+  for (int s = 0; s < BMS_MAX_SHIFTS; ++s) ua.xidx[s] = s < w.ns ? s : 0;
+  return ua;
+}
 
 template <typename T>
 int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
@@ -158,7 +187,7 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
                              skip, c->gram_variant, c->num_cu));
   MARK(3);
   HIP_TRY(c, launch_small_iter<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mx,
-                                  (cplx<T>*)w.Mp));
+                                  (cplx<T>*)w.Mp, (cplx<T>*)w.Mxd));
   MARK(4);
   // explicit Cholesky-QR Gram, only when the expansion lost its pivot
   HIP_TRY(c, launch_cholqr_gram<T>(c->stream, w.rows, w.n, w.Q, w.W, w.sm.alpha, w.sm.Gqr,
@@ -166,20 +195,7 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   MARK(5);
   HIP_TRY(c, launch_small_rho_explicit<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mp));
   MARK(6);
-  UpdateArgs<T, T> ua;
-  ua.rows = w.rows;
-  ua.n = w.n;
-  ua.ns = w.ns;
-  ua.Q = (cplx<T>*)w.Q;
-  ua.W = (const cplx<T>*)w.W;
-  ua.alpha = w.sm.alpha;
-  ua.rhoinv = w.sm.rhoinv;
-  ua.P = (cplx<T>*)w.P;
-  ua.X = (cplx<T>*)w.X;
-  ua.Mx = (const cplx<T>*)w.Mx;
-  ua.Mp = (const cplx<T>*)w.Mp;
-  ua.flags = w.flags;
-  for (int s = 0; s < BMS_MAX_SHIFTS; ++s) ua.xidx[s] = s < w.ns ? s : 0;
+  const UpdateArgs<T, T> ua = update_args<T>(w);
   // built-in default: the matrix-core kernel where it exists (n = 8, 16), else
   // four row chunks with one coefficient column at a time
   const int uv = c->update_variant;
@@ -337,8 +353,9 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
   // block vectors' precision (FP32 blocks in the mixed solver)
   sp.breakdown_tol = 10.0 * n * (mixed ? kEps32 : kEps);
   for (int s = 0; s < ns; ++s) sp.sigma[s] = sigma[s];
+  sp.pingpong = ns > 1 && use_pingpong(c, n);
   Work w;
-  if ((rc = alloc_work<T>(c, n, ns, max_iter, w))) return rc;
+  if ((rc = alloc_work<T>(c, n, ns, max_iter, sp.pingpong != 0, w))) return rc;
   void *R1 = nullptr, *R2 = nullptr, *R0 = nullptr;
   if (mixed) {
     size_t b64 = w.blk * sizeof(double2);
@@ -389,13 +406,15 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
     if (enqueued > (long)max_iter + 2L * K)  // the device stops itself at max_iter
       return set_err(c, BMS_EHIP, "device iteration control did not stop (iter %d)", hf.iter);
   }
+  // increments the two-iteration update still holds back
+  if (sp.pingpong) HIP_TRY(c, launch_update_drain<T>(c->stream, update_args<T>(w)));
   if (c->timing && hf.iter > 0) {
-    std::vector<int> nact(hf.iter);
-    HIP_TRY(c, hipMemcpyAsync(nact.data(), w.sm.nact_log, hf.iter * sizeof(int),
+    std::vector<int> units(hf.iter);
+    HIP_TRY(c, hipMemcpyAsync(units.data(), w.sm.upd_log, hf.iter * sizeof(int),
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double S = (double)w.blk * sizeof(cplx<T>);
-    for (int k = 0; k < hf.iter; ++k) c->kt_bytes[BMS_KERNEL_UPDATE] += (3.0 + 4.0 * nact[k]) * S;
+    for (int k = 0; k < hf.iter; ++k) c->kt_bytes[BMS_KERNEL_UPDATE] += units[k] * S;
   }
   if (mixed) {
     if ((rc = enqueue_reliable(c, w, sp, mass, B, Xout, xmap, R1, R2, R0, true))) return rc;

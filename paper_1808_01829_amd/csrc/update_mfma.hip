@@ -158,11 +158,13 @@ __device__ __forceinline__ void mfma_acc(typename Mf<F>::V (&d)[MfShape<N>::NT],
 
 // F: block and shift-update arithmetic type (double, or float in the mixed
 // solver). NTILE: 16-row tiles per wave (processed one after the other inside
-// each shift, so the coefficient operands are read from LDS once per wave and
-// shift). The active shifts come from one ballot; the P^(s), X^(s) tiles of
-// the next active shift are loaded into the registers the current tile has
-// just stored from, so they are in flight during the next shift's expansion
-// and barrier.
+// each shift). The shifts to update come from one ballot over their modes
+// (PP_*); the tiles of the next such shift are loaded into the registers the
+// current tile has just stored from, so they are in flight during the next
+// shift's expansion and barrier. Per mode a shift moves 4 (PP_NOW), 2
+// (PP_DEFER: P only), 5 (PP_FLUSH: both directions, X and the new direction)
+// or 3 (PP_DRAIN) block vectors: 7 every two iterations where the plain
+// update moves 8.
 template <typename F, int N, int NTILE>
 __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
   using S = MfShape<N>;
@@ -172,22 +174,26 @@ __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
   // per-wave layout change of Q, then the double-buffered shift operands (F)
   constexpr int QBYTES = 2 * S::BSZ * 8 + 2 * N * N * 16;
   constexpr int TBYTES = MF_WAVES * NTILE * 16 * S::NR * 8;
-  constexpr int SBYTES = 2 * 2 * S::BSZ * (int)sizeof(F);
+  constexpr int SBYTES = 2 * 3 * S::BSZ * (int)sizeof(F);
   constexpr int LBYTES = QBYTES > SBYTES ? (QBYTES > TBYTES ? QBYTES : TBYTES)
                                          : (SBYTES > TBYTES ? SBYTES : TBYTES);
   __shared__ __align__(16) unsigned char lds[LBYTES];
   double* qb0 = (double*)lds;
   double* qb1 = qb0 + S::BSZ;
   double2* cs = (double2*)(qb1 + S::BSZ);  // alpha, rho^-1
-  F* sb = (F*)lds;                         // [2][2][BSZ]
-  const SolverFlags* fl = a.flags;
+  F* sb = (F*)lds;                         // [2][3][BSZ]
+  SolverFlags* fl = a.flags;
   if (fl->halted) return;
   const int tid = threadIdx.x;
+  // the next small step applies this update's modes (nothing else in this
+  // kernel reads upd_done)
+  if (blockIdx.x == 0 && tid == 0) fl->upd_done = fl->iter;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int rows = a.rows, ns = a.ns;
+  const size_t blk = (size_t)rows * N;
   const int tile0 = (blockIdx.x * MF_WAVES + wave) * NTILE;
-  unsigned long long mask = __ballot(lane < ns && fl->active[lane] != 0);
+  unsigned long long mask = __ballot(lane < ns && fl->pp_mode[lane] != PP_NONE);
 
   // coefficients of the Q step: B0 = rho^-1, B1 = -alpha rho^-1
   for (int e = tid; e < N * N; e += BMS_WG) {
@@ -255,36 +261,47 @@ __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
     __syncthreads();  // the shift operands overwrite this LDS
   }
 
-  F pa[NTILE][S::KS];
+  // direction buffer b of shift s, and the tiles a shift's mode reads
+  auto pbuf = [&](int s, int b) { return a.P + ((size_t)b * ns + s) * blk; };
+  F pa[NTILE][S::KS], pb[NTILE][S::KS];
   VF xa[NTILE][S::NT];
+  auto fetch = [&](int s, int t) {
+    const int m = __builtin_amdgcn_readfirstlane(fl->pp_mode[s]);
+    const int cb = __builtin_amdgcn_readfirstlane(fl->pp_cur[s]);
+    const int r0 = (tile0 + t) * 16;
+    if (m != PP_DRAIN) aload<N>(pbuf(s, cb), r0 + c, rows, g, pa[t]);
+    if (m == PP_FLUSH || m == PP_DRAIN) aload<N>(pbuf(s, cb ^ 1), r0 + c, rows, g, pb[t]);
+    if (m != PP_DEFER) dload<N, F>(a.X + (size_t)a.xidx[s] * blk, r0, rows, g, c, xa[t]);
+  };
   int s = mask ? __ffsll((long long)mask) - 1 : -1;
   if (s >= 0) {
 #pragma unroll
-    for (int t = 0; t < NTILE; ++t) {
-      const int r0 = (tile0 + t) * 16;
-      aload<N>(a.P + (size_t)s * rows * N, r0 + c, rows, g, pa[t]);
-      dload<N, F>(a.X + (size_t)a.xidx[s] * rows * N, r0, rows, g, c, xa[t]);
-    }
+    for (int t = 0; t < NTILE; ++t) fetch(s, t);
   }
   int buf = 0;
   while (s >= 0) {
     mask &= mask - 1;
     const int s2 = mask ? __ffsll((long long)mask) - 1 : -1;
-    F* bx = sb + (2 * buf) * S::BSZ;
+    const int m = __builtin_amdgcn_readfirstlane(fl->pp_mode[s]);
+    const int cb = __builtin_amdgcn_readfirstlane(fl->pp_cur[s]);
+    const bool take_x = m == PP_NOW || m == PP_FLUSH;   // X += P_k Mx_k
+    const bool take_d = m == PP_FLUSH || m == PP_DRAIN;  // X += P_k-1 Mxd
+    const bool new_p = m != PP_DRAIN;                    // P_k+1 = Q_k+1 + P_k Mp_k
+    F* bx = sb + (3 * buf) * S::BSZ;
     F* bp = bx + S::BSZ;
+    F* bd = bp + S::BSZ;
     const CF* mx = a.Mx + (size_t)s * N * N;
     const CF* mp = a.Mp + (size_t)s * N * N;
+    const CF* md = a.Mxd + (size_t)s * N * N;
     for (int e = tid; e < N * N; e += BMS_WG) {
       int i = e / N, j = e - (e / N) * N;
-      bput<N>(bx, i, j, to_d(mx[e]));
-      bput<N>(bp, i, j, to_d(mp[e]));
+      if (take_x) bput<N>(bx, i, j, to_d(mx[e]));
+      if (new_p) bput<N>(bp, i, j, to_d(mp[e]));
+      if (take_d) bput<N>(bd, i, j, to_d(md[e]));
     }
     __syncthreads();
-    F cx[S::KS][S::NT], cp[S::KS][S::NT];
-    bload<N>(bx, lane, cx);
-    bload<N>(bp, lane, cp);
-    CF* P = a.P + (size_t)s * rows * N;
-    CF* X = a.X + (size_t)a.xidx[s] * rows * N;
+    CF* X = a.X + (size_t)a.xidx[s] * blk;
+    CF* Pout = pbuf(s, m == PP_NOW ? cb : cb ^ 1);
 #pragma unroll
     for (int t = 0; t < NTILE; ++t) {
       const int r0 = (tile0 + t) * 16;
@@ -294,21 +311,67 @@ __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
         pn[nt] = qn[t][nt];
         dx[nt] = VF{0, 0, 0, 0};
       }
-      // the increment P^(s) Mx is formed on its own and added to X once, so
-      // X (large next to one step's increment) is rounded once per iteration
-      mfma_acc<N>(dx, pa[t], cx);
-      mfma_acc<N>(pn, pa[t], cp);
-#pragma unroll
-      for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
-      dstore<N, F>(X, r0, rows, g, c, xa[t]);
-      dstore<N, F>(P, r0, rows, g, c, pn);
-      if (s2 >= 0) {
-        aload<N>(a.P + (size_t)s2 * rows * N, r0 + c, rows, g, pa[t]);
-        dload<N, F>(a.X + (size_t)a.xidx[s2] * rows * N, r0, rows, g, c, xa[t]);
+      // the increment (one or two iterations') is formed on its own and added
+      // to X once, so X (large next to one step's increment) is rounded once
+      F co[S::KS][S::NT];
+      if (take_d) {
+        bload<N>(bd, lane, co);
+        mfma_acc<N>(dx, pb[t], co);
       }
+      if (take_x) {
+        bload<N>(bx, lane, co);
+        mfma_acc<N>(dx, pa[t], co);
+      }
+      if (new_p) {
+        bload<N>(bp, lane, co);
+        mfma_acc<N>(pn, pa[t], co);
+      }
+      if (m != PP_DEFER) {
+#pragma unroll
+        for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
+        dstore<N, F>(X, r0, rows, g, c, xa[t]);
+      }
+      if (new_p) dstore<N, F>(Pout, r0, rows, g, c, pn);
+      if (s2 >= 0) fetch(s2, t);
     }
     s = s2;
     buf ^= 1;
+  }
+}
+
+// After the last iteration: every increment still pending (also one whose
+// deferring update has not been applied by a small step yet) is added, X^(s)
+// += P^(s)_prev Mxd^(s). One thread per complex entry of a row block.
+template <typename F>
+__global__ __launch_bounds__(BMS_WG) void k_update_drain(UpdateArgs<F, F> a) {
+  using CF = cplx<F>;
+  const SolverFlags* fl = a.flags;
+  const int n = a.n, ns = a.ns;
+  const size_t blk = (size_t)a.rows * n;
+  const size_t e = (size_t)blockIdx.x * BMS_WG + threadIdx.x;
+  if (e >= blk) return;
+  const size_t row = e / n;
+  const int j = (int)(e - row * n);
+  for (int s = 1; s < ns; ++s) {
+    int m = fl->upd_done != fl->pp_done[s] ? fl->pp_mode[s] : PP_NONE;
+    int pend = fl->pp_pend[s], cb = fl->pp_cur[s];
+    const CF* md = a.Mxd + (size_t)s * n * n;
+    if (m == PP_DEFER) {
+      pend = 1;
+      cb ^= 1;
+      md = a.Mx + (size_t)s * n * n;
+    } else if (m == PP_FLUSH) {
+      pend = 0;
+      cb ^= 1;
+    } else if (m == PP_DRAIN) {
+      pend = 0;
+    }
+    if (!pend) continue;
+    const CF* P = a.P + ((size_t)(cb ^ 1) * ns + s) * blk + row * n;
+    CF acc = czero<CF>();
+    for (int k = 0; k < n; ++k) acc = cfma(P[k], md[(size_t)k * n + j], acc);
+    CF* X = a.X + (size_t)a.xidx[s] * blk + e;
+    *X = cadd(*X, acc);
   }
 }
 
@@ -335,6 +398,15 @@ hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<F, F>& a, bool tw
   }
 }
 
+template <typename F>
+hipError_t launch_update_drain(hipStream_t st, const UpdateArgs<F, F>& a) {
+  const size_t blk = (size_t)a.rows * a.n;
+  k_update_drain<F><<<(unsigned)((blk + BMS_WG - 1) / BMS_WG), BMS_WG, 0, st>>>(a);
+  return hipGetLastError();
+}
+
 template hipError_t launch_update_mfma<double>(hipStream_t, const UpdateArgs<double, double>&,
                                                bool);
 template hipError_t launch_update_mfma<float>(hipStream_t, const UpdateArgs<float, float>&, bool);
+template hipError_t launch_update_drain<double>(hipStream_t, const UpdateArgs<double, double>&);
+template hipError_t launch_update_drain<float>(hipStream_t, const UpdateArgs<float, float>&);

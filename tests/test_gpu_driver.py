@@ -60,7 +60,7 @@ def test_autotune_keeps_solves_correct(torch):
         # the candidates bms_autotune times at n = 16 (hop: both kernels, both
         # traversals; Gram: the two streaming depths and the LDS kernel)
         assert chosen["hop"] in (-1, 0, 1, 2, 3) and chosen["gram"] in (1, 2, 3)
-        assert chosen["update"] in (0, 2, 4, 5)
+        assert chosen["update"] in (0, 2, 4, 5, 6)
         X, st = ctx.solve(0.05, r.beta, Bd, tol=1e-10, precision=prec)
         tr = O.true_residuals((6, 4, 4, 6), BC, U, 0.05, r.beta, B, to_np(X))
         assert tr.max() <= 1e-10

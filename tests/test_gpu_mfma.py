@@ -2,8 +2,9 @@
 
 After k block iterations (max_iter = k, no refinement) the solutions X^(s)_k
 of the HIP solver are compared with the oracle's sbcgrq run for the same k
-iterations, for each pairing of update kernel (MFMA = the default for FP64 at
-n = 8, 16; vector = variant 2) and Gram kernel (MFMA with 8 or 4 row steps in
+iterations, for each pairing of update kernel (MFMA = the default at n = 8, 16, with
+the shifted solutions updated every second iteration, variants 4 and 5;
+MFMA updating every shift every iteration = variant 6; vector = variant 2) and Gram kernel (MFMA with 8 or 4 row steps in
 flight = the default and variant 1; vector = variant 0). Row counts 3*Vh that
 are not a multiple of the 16-row tile, and blocks whose row range is not a
 multiple of the 4-row Gram step, exercise the ragged edges.
@@ -34,7 +35,8 @@ CASES = [
 
 
 # (update variant, Gram variant)
-KERNELS = [(-1, -1), (2, 0), (4, 1), (2, 2), (5, 0), (2, 3), (5, 3), (4, 0), (4, 4), (5, 5)]
+KERNELS = [(-1, -1), (2, 0), (4, 1), (2, 2), (5, 0), (2, 3), (5, 3), (4, 0), (4, 4), (5, 5),
+           (6, -1), (6, 1)]
 
 
 @pytest.mark.parametrize("dims,n,k", CASES)
@@ -78,13 +80,13 @@ def test_mfma_full_solve_converges(torch, n):
     ctx = bms.Context(dims, BC)
     ctx.set_gauge(to_dev(torch, U))
     res = {}
-    for variant in (4, 2):
+    for variant in (4, 6, 2):
         ctx.set_variant(bms.BMS_KERNEL_UPDATE, variant)
         X, st = ctx.solve(mass, r.beta, to_dev(torch, B), tol=1e-10)
         tr = O.true_residuals(dims, BC, U, mass, r.beta, B, to_np(X))
         assert tr.max() <= 1e-10
         res[variant] = st["iterations"]
-    assert abs(res[4] - res[2]) <= 1
+    assert abs(res[4] - res[2]) <= 1 and abs(res[6] - res[2]) <= 1
 
 
 @pytest.mark.parametrize("n", [8, 16])
