@@ -88,6 +88,28 @@ __device__ __forceinline__ void bload(const F* B, int lane, F (&b)[MfShape<N>::K
     for (int nt = 0; nt < S::NT; ++nt) b[ks][nt] = B[(ks * 64 + lane) * S::NT + nt];
 }
 
+// The shift coefficients are kept in LDS as the complex n x n matrix, (re,
+// im) pairs, a quarter of the expanded form; each lane forms its B-operand
+// reals from it: B[2k][j] = Re M[k][j], B[2k][n+j] = Im, B[2k+1][j] = -Im,
+// B[2k+1][n+j] = Re, at kk = g*KS + ks, flat = nt*16 + c.
+// d += a * B(M), the B operands read from LDS one k-step at a time (few
+// registers live: the kernel keeps four waves per SIMD)
+template <int N, typename F>
+__device__ __forceinline__ void mfma_acc_c(typename Mf<F>::V (&d)[MfShape<N>::NT],
+                                           const F (&a)[MfShape<N>::KS], const F* M, int g,
+                                           int c) {
+  using S = MfShape<N>;
+#pragma unroll
+  for (int ks = 0; ks < S::KS; ++ks)
+#pragma unroll
+    for (int nt = 0; nt < S::NT; ++nt) {
+      const int kk = g * S::KS + ks, flat = nt * 16 + c;
+      const int k = kk >> 1, rim = kk & 1, j = flat % N, cim = flat / N;
+      const F v = M[2 * (k * N + j) + (rim ^ cim)];
+      d[nt] = Mf<F>::mfma(a[ks], rim && !cim ? -v : v, d[nt]);
+    }
+}
+
 // A-operand reals of one tile row (row r, reals g*KS .. g*KS+KS-1) in the
 // arithmetic type F. Rows past the end read row 0 and are zeroed, with no
 // branch around the loads (so the loads of several tiles stay in flight).
@@ -165,8 +187,12 @@ __device__ __forceinline__ void mfma_acc(typename Mf<F>::V (&d)[MfShape<N>::NT],
 // (PP_DEFER: P only), 5 (PP_FLUSH: both directions, X and the new direction)
 // or 3 (PP_DRAIN) block vectors: 7 every two iterations where the plain
 // update moves 8.
+// One tile per wave: four waves per SIMD (the register count the compiler
+// picks by itself leaves three, and this streaming kernel runs at the rate
+// of its loads in flight).
 template <typename F, int N, int NTILE>
-__global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
+__global__ __launch_bounds__(BMS_WG) __attribute__((amdgpu_waves_per_eu(NTILE == 1 ? 4 : 1)))
+void k_update_mfma(UpdateArgs<F, F> a) {
   using S = MfShape<N>;
   using CF = cplx<F>;
   using VF = typename Mf<F>::V;
@@ -174,14 +200,14 @@ __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
   // per-wave layout change of Q, then the double-buffered shift operands (F)
   constexpr int QBYTES = 2 * S::BSZ * 8 + 2 * N * N * 16;
   constexpr int TBYTES = MF_WAVES * NTILE * 16 * S::NR * 8;
-  constexpr int SBYTES = 2 * 3 * S::BSZ * (int)sizeof(F);
+  constexpr int SBYTES = 2 * 3 * 2 * N * N * (int)sizeof(F);
   constexpr int LBYTES = QBYTES > SBYTES ? (QBYTES > TBYTES ? QBYTES : TBYTES)
                                          : (SBYTES > TBYTES ? SBYTES : TBYTES);
   __shared__ __align__(16) unsigned char lds[LBYTES];
   double* qb0 = (double*)lds;
   double* qb1 = qb0 + S::BSZ;
   double2* cs = (double2*)(qb1 + S::BSZ);  // alpha, rho^-1
-  F* sb = (F*)lds;                         // [2][3][BSZ]
+  F* sb = (F*)lds;                         // [2][3][N*N] complex
   SolverFlags* fl = a.flags;
   if (fl->halted) return;
   const int tid = threadIdx.x;
@@ -287,17 +313,25 @@ __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
     const bool take_x = m == PP_NOW || m == PP_FLUSH;   // X += P_k Mx_k
     const bool take_d = m == PP_FLUSH || m == PP_DRAIN;  // X += P_k-1 Mxd
     const bool new_p = m != PP_DRAIN;                    // P_k+1 = Q_k+1 + P_k Mp_k
-    F* bx = sb + (3 * buf) * S::BSZ;
-    F* bp = bx + S::BSZ;
-    F* bd = bp + S::BSZ;
+    F* bx = sb + (3 * buf) * 2 * N * N;
+    F* bp = bx + 2 * N * N;
+    F* bd = bp + 2 * N * N;
     const CF* mx = a.Mx + (size_t)s * N * N;
     const CF* mp = a.Mp + (size_t)s * N * N;
     const CF* md = a.Mxd + (size_t)s * N * N;
     for (int e = tid; e < N * N; e += BMS_WG) {
-      int i = e / N, j = e - (e / N) * N;
-      if (take_x) bput<N>(bx, i, j, to_d(mx[e]));
-      if (new_p) bput<N>(bp, i, j, to_d(mp[e]));
-      if (take_d) bput<N>(bd, i, j, to_d(md[e]));
+      if (take_x) {
+        bx[2 * e] = mx[e].x;
+        bx[2 * e + 1] = mx[e].y;
+      }
+      if (new_p) {
+        bp[2 * e] = mp[e].x;
+        bp[2 * e + 1] = mp[e].y;
+      }
+      if (take_d) {
+        bd[2 * e] = md[e].x;
+        bd[2 * e + 1] = md[e].y;
+      }
     }
     __syncthreads();
     CF* X = a.X + (size_t)a.xidx[s] * blk;
@@ -313,19 +347,9 @@ __global__ __launch_bounds__(BMS_WG) void k_update_mfma(UpdateArgs<F, F> a) {
       }
       // the increment (one or two iterations') is formed on its own and added
       // to X once, so X (large next to one step's increment) is rounded once
-      F co[S::KS][S::NT];
-      if (take_d) {
-        bload<N>(bd, lane, co);
-        mfma_acc<N>(dx, pb[t], co);
-      }
-      if (take_x) {
-        bload<N>(bx, lane, co);
-        mfma_acc<N>(dx, pa[t], co);
-      }
-      if (new_p) {
-        bload<N>(bp, lane, co);
-        mfma_acc<N>(pn, pa[t], co);
-      }
+      if (take_d) mfma_acc_c<N>(dx, pb[t], bd, g, c);
+      if (take_x) mfma_acc_c<N>(dx, pa[t], bx, g, c);
+      if (new_p) mfma_acc_c<N>(pn, pa[t], bp, g, c);
       if (m != PP_DEFER) {
 #pragma unroll
         for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
