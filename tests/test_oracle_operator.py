@@ -36,6 +36,26 @@ def test_free_spectrum_4444_antiperiodic_t():
     assert np.abs(ev - expect).max() < 1e-12
 
 
+def test_free_spectrum_4444_golden():
+    # the stored closed-form spectrum (tests/golden/free_field_4444.txt, by
+    # momentum enumeration) against the oracle's dense operator
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "free_field_4444.txt")
+    table = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, shift, mult = line.split()
+        table.setdefault(name, []).append((float(shift), int(mult)))
+    m = 0.2
+    for name, bc in (("periodic", (1, 1, 1, 1)), ("antiperiodic_t", (1, 1, 1, -1))):
+        expect = np.sort(np.concatenate([np.full(k, m * m + lam) for lam, k in table[name]]))
+        assert expect.size == 384
+        A = O.dense_operator((4, 4, 4, 4), bc, unit_gauge((4, 4, 4, 4)), m, 0.0)
+        ev = np.sort(np.linalg.eigvalsh(A))
+        assert np.abs(ev - expect).max() < 1e-12, name
+
+
 @pytest.mark.parametrize("dims", [(2, 4, 6, 4), (4, 2, 2, 6)])
 @pytest.mark.parametrize("bc", BCS)
 def test_free_spectrum_anisotropic(dims, bc):
