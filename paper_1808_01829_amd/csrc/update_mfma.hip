@@ -187,11 +187,14 @@ __device__ __forceinline__ void mfma_acc(typename Mf<F>::V (&d)[MfShape<N>::NT],
 // (PP_DEFER: P only), 5 (PP_FLUSH: both directions, X and the new direction)
 // or 3 (PP_DRAIN) block vectors: 7 every two iterations where the plain
 // update moves 8.
-// One tile per wave: four waves per SIMD (the register count the compiler
-// picks by itself leaves three, and this streaming kernel runs at the rate
-// of its loads in flight).
+// FP32 blocks, one tile per wave: four waves per SIMD or more (the register
+// count the compiler picks by itself leaves fewer; at 32^4 the mixed solve
+// took 7.26 instead of 7.38 s). In FP64 four waves need spills, whose scratch
+// traffic reached HBM (6-9 % over the algorithmic bytes) for no gain in time,
+// so FP64 keeps three.
 template <typename F, int N, int NTILE>
-__global__ __launch_bounds__(BMS_WG) __attribute__((amdgpu_waves_per_eu(NTILE == 1 ? 4 : 1)))
+__global__ __launch_bounds__(BMS_WG)
+__attribute__((amdgpu_waves_per_eu(NTILE == 1 && sizeof(F) == 4 ? 4 : 1)))
 void k_update_mfma(UpdateArgs<F, F> a) {
   using S = MfShape<N>;
   using CF = cplx<F>;
