@@ -1,6 +1,6 @@
 // The n_pf x n_pf FP64 algebra of Algorithm 1 on the device: Cholesky-QR
 // factors, alpha_k = (P^H (A+s0) P)^-1, and the two coupled two-term
-// recurrences of the shifted systems (Algorithm 1, lines 10-11):
+// recurrences of the shifted systems (Algorithm 1, the shift-recurrence steps):
 //   beta^(s)_k  = (1 + (s_s - s_0) alpha_k
 //                  + alpha_k rho_{k-1} alpha_{k-1}^-1 (1 - beta^(s)_{k-1}) rho_{k-1}^dag)^-1
 //   alpha^(s)_k = beta^(s)_k alpha_k rho_{k-1} alpha_{k-1}^-1 alpha^(s)_{k-1}
@@ -424,7 +424,7 @@ __device__ void pp_commit(SolverFlags* fl, int q, const C* Mx, C* Mxd, int nn) {
 }
 
 // One iteration's n x n work, after G4 = [P^H W, Q^H W, W^H W, Q^H Q]:
-//   alpha_k = (P^H W)^-1; beta^(s)_k, alpha^(s)_k (Algorithm 1, lines 10-11);
+//   alpha_k = (P^H W)^-1; beta^(s)_k, alpha^(s)_k (Algorithm 1, shift recurrences);
 //   V^H V from the expansion, rho_k = chol(V^H V)^H; then rho_part.
 // If that Cholesky loses its pivot, need_explicit is raised and the explicit
 // Gram of V plus k_small_rho_explicit finish the iteration instead.
