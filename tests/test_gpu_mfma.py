@@ -89,6 +89,35 @@ def test_mfma_full_solve_converges(torch, n):
     assert abs(res[4] - res[2]) <= 1 and abs(res[6] - res[2]) <= 1
 
 
+@pytest.mark.parametrize("n,max_iter", [(8, 10000), (16, 10000), (16, 23), (8, 24)])
+def test_two_iteration_update_matches_every_iteration(torch, n, max_iter):
+    """Shifts freeze at different iterations, after either half of the
+    two-iteration cycle, and the solve may stop at max_iter with increments
+    pending: the solutions equal those of the every-iteration update (variant
+    6) up to the order of the additions into X, and the residual estimates
+    of the two forms are the same."""
+    from paper_1808_01829_amd import bms
+    dims = (6, 4, 4, 6)
+    r = configs.workload_coefficients("c2")
+    U = random_gauge(dims, 0.5, 41 + n)
+    B = gaussian_block(dims, n, 43 + n)
+    ctx = bms.Context(dims, BC)
+    ctx.set_gauge(to_dev(torch, U))
+    out = {}
+    for upd in (6, 4, 5):
+        ctx.set_variant(bms.BMS_KERNEL_UPDATE, upd)
+        X, st = ctx.solve(0.05, r.beta, to_dev(torch, B), tol=1e-10, max_iter=max_iter,
+                          max_refine=0, raise_on_error=False)
+        out[upd] = (to_np(X), st)
+    X6, st6 = out[6]
+    for upd in (4, 5):
+        X, st = out[upd]
+        assert st["iterations"] == st6["iterations"] and st["status"] == st6["status"]
+        for s in range(len(r.beta)):
+            ref = np.linalg.norm(X6[s])
+            assert np.linalg.norm(X[s] - X6[s]) / ref <= 1e-12, (upd, s)
+
+
 @pytest.mark.parametrize("n", [8, 16])
 def test_mfma_gram_mixed_precision_solve(torch, n):
     """FP32 inputs to the MFMA Gram (FP64 accumulation) in the mixed solver."""
