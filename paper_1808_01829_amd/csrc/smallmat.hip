@@ -24,13 +24,20 @@ __device__ __forceinline__ double2 crecip(double2 a) {
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
 // C = op(A) op(B), op 0 = identity, 1 = conjugate transpose. C must not alias.
+// The k loops of these helpers are unrolled so that several LDS loads are in
+// flight (their latency, not arithmetic, sets the time of the small step);
+// the order of the additions is unchanged.
 __device__ void sm_mm(double2* C, const double2* A, int ta, const double2* B, int tb, int n) {
   for (int e = threadIdx.x; e < n * n; e += BMS_WG) {
     int i = e / n, j = e - (e / n) * n;
+    const int a0 = ta ? i : i * n, as = ta ? n : 1;
+    const int b0 = tb ? j * n : j, bs = tb ? 1 : n;
     double2 s = make_double2(0, 0);
+#pragma unroll 4
     for (int k = 0; k < n; ++k) {
-      double2 a = ta ? cconj(A[k * n + i]) : A[i * n + k];
-      double2 b = tb ? cconj(B[j * n + k]) : B[k * n + j];
+      double2 a = A[a0 + k * as], b = B[b0 + k * bs];
+      if (ta) a = cconj(a);
+      if (tb) b = cconj(b);
       s = cfma(a, b, s);
     }
     C[e] = s;
@@ -77,6 +84,7 @@ __device__ int sm_chol_upper(double2* R, const double2* G, int n, double tol) {
   for (int j = 0; j < n; ++j) {
     if (threadIdx.x == 0) {
       double d = G[j * n + j].x;
+#pragma unroll 4
       for (int k = 0; k < j; ++k) d -= cabs2(R[k * n + j]);
       if (!(d == d) || !(trace == trace) || !(fabs(trace) < 1e300)) status = BMS_ENAN;
       else if (!(d > tol * trace)) status = BMS_EBREAKDOWN;
@@ -87,6 +95,7 @@ __device__ int sm_chol_upper(double2* R, const double2* G, int n, double tol) {
     double djj = R[j * n + j].x;
     for (int i = j + 1 + threadIdx.x; i < n; i += BMS_WG) {
       double2 s = G[j * n + i];
+#pragma unroll 4
       for (int k = 0; k < j; ++k) s = csub(s, cmul(cconj(R[k * n + j]), R[k * n + i]));
       R[j * n + i] = cdiv_real(s, djj);
     }
@@ -104,6 +113,7 @@ __device__ void sm_triinv_upper(double2* X, const double2* R, int n) {
         continue;
       }
       double2 s = make_double2(i == j ? 1.0 : 0.0, 0);
+#pragma unroll 4
       for (int k = i + 1; k <= j; ++k) s = csub(s, cmul(R[i * n + k], X[k * n + j]));
       X[i * n + j] = cdiv_real(s, R[i * n + i].x);
     }
@@ -123,6 +133,7 @@ __device__ int sm_inv_general(double2* Ainv, double2* A, int n) {
     if (threadIdx.x == 0) {
       int p = c;
       double best = cabs2(A[c * n + c]);
+#pragma unroll 4
       for (int r = c + 1; r < n; ++r) {
         double v = cabs2(A[r * n + c]);
         if (v > best) {
@@ -374,16 +385,21 @@ __device__ void rho_part(const SmallParams& p, const SmallState& s, SolverFlags*
     sm_mm(T0, T1, 0, R, 1, n);  // beta^(s)_k rho_k^dag
     sm_store_t(Mp + (size_t)q * nn, T0, n);
   }
-  // relative residual estimate: max_i |delta^(s) e_i| / |b_i|
+  // relative residual estimate: max_i |delta^(s) e_i| / |b_i| (a thread per
+  // column, then the maximum)
+  __shared__ double colr[NMAX];
+  for (int i = threadIdx.x; i < n; i += BMS_WG) {
+    double c = 0;
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) c += cabs2(D[k * n + i]);
+    double r = sqrt(c) / s.norm0[i];
+    if (!(r == r)) r = 1e300;
+    colr[i] = r;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     double m = 0;
-    for (int i = 0; i < n; ++i) {
-      double c = 0;
-      for (int k = 0; k < n; ++k) c += cabs2(D[k * n + i]);
-      double r = sqrt(c) / s.norm0[i];
-      if (!(r == r)) r = 1e300;
-      m = r > m ? r : m;
-    }
+    for (int i = 0; i < n; ++i) m = colr[i] > m ? colr[i] : m;
     colmax = m;
   }
   __syncthreads();
