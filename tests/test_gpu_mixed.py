@@ -70,3 +70,27 @@ def test_mixed_16x16x16x16_workload(torch):
     assert tr.max() <= w["tol"]
     # the library's own FP64 residual check agrees with the oracle's
     assert np.allclose(np.asarray(st["true_residual"]), tr, rtol=1e-3, atol=1e-14)
+
+
+def test_mixed_32x32x32x32_benchmark_solve_sampled(torch):
+    """The benchmarked solve at full size (32^4, n_pf = 16, 20 poles, mixed,
+    default kernels, the benchmark's seeds): columns 0, 7 and 15 of every shift
+    have true FP64 residual <= tol recomputed with the oracle's operator, and
+    the library's own residual check agrees with it."""
+    from paper_1808_01829_amd import bms
+    w = configs.WORKLOADS["c5"]
+    r = configs.workload_coefficients("c5")
+    dims, n, m = w["dims"], w["n"], w["mass"]
+    U = random_gauge(dims, w["eps"], 1000 * w["id"])
+    B = gaussian_block(dims, n, 1000 * w["id"] + 1)
+    c = _ctx(torch, dims, U)
+    X, st = c.solve(m, r.beta, to_dev(torch, B), tol=w["tol"], precision=bms.BMS_PREC_MIXED,
+                    reliable_interval=w["reliable"])
+    assert st["converged"]
+    cols = [0, 7, 15]
+    Xs = np.ascontiguousarray(to_np(X[..., cols]))
+    del X
+    tr = O.true_residuals(dims, BC, U, m, r.beta, np.ascontiguousarray(B[..., cols]), Xs)
+    assert tr.max() <= w["tol"]
+    lib = np.asarray(st["true_residual"])[:, cols]
+    assert np.allclose(lib, tr, rtol=1e-3, atol=1e-14)
