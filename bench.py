@@ -157,6 +157,25 @@ def per_vector(ctx, bms, m, r, Bd, tol, cols, torch):
 FP64_VALU_PEAK_TFLOPS = 78.6
 
 
+def action_measure(ctx, r, Bd, X, torch, reps=5):
+    """The action S_i = Re phi_i^dag (a0 phi_i + sum_j alpha_j X_ij) of the
+    timed solve's own solutions: wall time per bms_action call (the reduction
+    kernel, its partial sums and the read-back of n values), against its
+    algorithmic bytes (B and every X read once)."""
+    alpha = list(r.alpha)
+    ctx.action(r.a0, alpha, Bd, X)  # warm-up (scratch allocation)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        S = ctx.action(r.a0, alpha, Bd, X)
+    us = (time.perf_counter() - t) / reps * 1e6
+    nbytes = (1 + X.shape[0]) * Bd.numel() * Bd.element_size()
+    gbs = nbytes / (us * 1e-6) / 1e9
+    return dict(call="bms_action", avg_us=round(us, 1), algorithmic_bytes=int(nbytes),
+                gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                columns=len(S), note="wall time per call, read-back included")
+
+
 def force_measure(bms, torch, np, configs, reps=3):
     """The force kernel at the force workload (K = n_pf x N_s columns), random
     solutions (its cost does not depend on their values): time, algorithmic
@@ -289,6 +308,10 @@ def main():
                     traffic=stored_traffic(args.workload, prec, dom),
                     algorithmic_bytes_per_launch=round(dk["bytes"] / dk["launches"]))
 
+    action = action_measure(ctx, r, Bd, X, torch)
+    log("bench: action %s" % action)
+    del X
+
     # per-vector baseline: same library, n = 1, FP64, one column at a time
     pv_iters = [0]
     pv_rate = float("nan")
@@ -384,6 +407,7 @@ def main():
                     hbm_frac=round(kernels["hop"]["gbs"] / HBM_PEAK_GBS, 4)
                     if "hop" in kernels else None),
         seeds=seeds,
+        action=action,
         force=force,
         per_vector=dict(value=round(pv_rate, 4) if pv_rate == pv_rate else None,
                         unit="RHS-solves/s", columns=args.baseline_cols,
