@@ -22,8 +22,10 @@
 //   D: lane (g, c) holds four rows of the tile at real output column nt*16 + c,
 //      which for n = 16 is (Re, Im) of complex column c in the two n-tiles: one
 //      complex per row, so X and P are read and written as whole complex numbers.
-// The coefficient matrices are expanded into that B layout in LDS once per
-// work-group and shift (double-buffered, one barrier per shift).
+// The Q step's two coefficient matrices are expanded into that B layout in
+// LDS once per work-group. The shift coefficients are kept in LDS as complex
+// n x n matrices (double-buffered, one barrier per shift), and each lane
+// forms its B operands from them one k-step at a time.
 #include "blas.h"
 
 namespace {
