@@ -1,0 +1,127 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each case plants one mistake in a copy of the C oracle (oracle/staggered.c,
+edited as text and compiled into a temporary directory; the oracle itself is
+not touched), loads that copy through a second instance of the oracle's
+Python module, and checks that the pin meant to catch it rejects it. The
+mistakes are the kind a reading of the operator or of multi-shift CG could
+make: a dropped dagger, a wrong staggered phase, a lost factor 1/2, a
+boundary factor on the wrong link, a wrong power in the shifted recurrence.
+"""
+import importlib.util
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1808_01829_amd.inputs import configs, gaussian_block, random_gauge, unit_gauge
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "staggered.c")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "free_field_4444.txt")
+
+MUTANTS = {
+    "dagger dropped on the backward hop":
+        ("c_cjmul(ub[3 * b + a], pb[b])", "c_mul(ub[3 * a + b], pb[b])", "antihermitian"),
+    "staggered phase summed over nu <= mu":
+        ("for (int nu = 0; nu < mu; ++nu) s += c[nu];",
+         "for (int nu = 0; nu <= mu; ++nu) s += c[nu];", "spectrum"),
+    "factor 1/2 dropped":
+        ("double e = 0.5 * eta(c, mu);", "double e = eta(c, mu);", "spectrum"),
+    "forward boundary factor on the backward hop":
+        ("acc[a] = c_sub(acc[a], c_scale(t, e * bb));",
+         "acc[a] = c_sub(acc[a], c_scale(t, e * bf));", "spectrum"),
+    "shifted direction update with zeta ratio to the first power":
+        ("double bs = beta * ratio * ratio;", "double bs = beta * ratio;", "mscg"),
+}
+
+
+def _mutant(tmp_path, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, old  # the planted edit hits exactly one place
+    d = tmp_path / "oracle_mutant"
+    d.mkdir()
+    (d / "staggered.c").write_text(src.replace(old, new))
+    so = d / "liboracle.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o",
+                           str(so), str(d / "staggered.c"), "-lm"])
+    spec = importlib.util.spec_from_file_location("oracle_mutant",
+                                                  os.path.join(ROOT, "oracle", "oracle.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.HERE = str(d)  # lib() loads the mutant (newer than its source, so no rebuild)
+    return mod
+
+
+def _golden():
+    table = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, shift, mult = line.split()
+        table.setdefault(name, []).append((float(shift), int(mult)))
+    return table
+
+
+def spectrum_error(mod):
+    """Largest distance of the free 4^4 spectrum (both boundary conditions)
+    from the stored closed form."""
+    m, err = 0.2, 0.0
+    table = _golden()
+    for name, bc in (("periodic", (1, 1, 1, 1)), ("antiperiodic_t", (1, 1, 1, -1))):
+        expect = np.sort(np.concatenate([np.full(k, m * m + lam) for lam, k in table[name]]))
+        A = mod.dense_operator((4, 4, 4, 4), bc, unit_gauge((4, 4, 4, 4)), m, 0.0)
+        ev = np.sort(np.linalg.eigvalsh(A))
+        err = max(err, float(np.abs(ev - expect).max()))
+    return err
+
+
+def antihermitian_error(mod):
+    """|D_eo + D_oe^dag| / |D_oe| on a random gauge field."""
+    dims, bc = (2, 4, 2, 6), (1, 1, 1, -1)
+    U = random_gauge(dims, 0.9, 3)
+    n = 3 * int(np.prod(dims)) // 2
+    Doe = np.empty((n, n), dtype=complex)
+    Deo = np.empty((n, n), dtype=complex)
+    e = np.zeros(n, dtype=complex)
+    for k in range(n):
+        e[:] = 0
+        e[k] = 1
+        Doe[:, k] = mod.dslash_half(dims, bc, U, 1, e.reshape(-1, 3)).reshape(-1)
+        Deo[:, k] = mod.dslash_half(dims, bc, U, 0, e.reshape(-1, 3)).reshape(-1)
+    return float(np.linalg.norm(Deo + Doe.conj().T) / np.linalg.norm(Doe))
+
+
+def mscg_error(mod):
+    """Largest relative distance of the multi-shift CG solutions from dense
+    solves on a 2^4 lattice."""
+    dims, bc = (2, 2, 2, 2), (1, 1, 1, -1)
+    r = configs.workload_coefficients("c2")
+    U = random_gauge(dims, 0.9, 11)
+    B = gaussian_block(dims, 2, 12)
+    X, _ = mod.solve_block(dims, bc, U, 0.1, r.beta, B, 1e-13)
+    err = 0.0
+    for s, sig in enumerate(r.beta):
+        A = O.dense_operator(dims, bc, U, 0.1, sig)
+        xd = np.linalg.solve(A, B.reshape(-1, B.shape[2])).reshape(B.shape)
+        err = max(err, float(np.linalg.norm(X[s] - xd) / np.linalg.norm(xd)))
+    return err
+
+
+CHECKS = {"spectrum": (spectrum_error, 1e-12), "antihermitian": (antihermitian_error, 1e-13),
+          "mscg": (mscg_error, 1e-10)}
+
+
+def test_pins_pass_on_the_oracle():
+    for name, (check, tol) in CHECKS.items():
+        assert check(O) < tol, name
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new, pin = MUTANTS[name]
+    mod = _mutant(tmp_path, old, new)
+    check, tol = CHECKS[pin]
+    assert check(mod) > 1e3 * tol, name
