@@ -1,12 +1,14 @@
 """The oracle's pins catch plausible mistakes (CPU only).
 
-Each case plants one mistake in a copy of the C oracle (oracle/staggered.c,
-edited as text and compiled into a temporary directory; the oracle itself is
-not touched), loads that copy through a second instance of the oracle's
-Python module, and checks that the pin meant to catch it rejects it. The
-mistakes are the kind a reading of the operator or of multi-shift CG could
-make: a dropped dagger, a wrong staggered phase, a lost factor 1/2, a
-boundary factor on the wrong link, a wrong power in the shifted recurrence.
+Each case plants one mistake in a copy of the oracle and checks that the pin
+meant to catch it rejects it; the oracle itself is not touched. Mistakes in
+the C operator and multi-shift CG (oracle/staggered.c) are compiled from an
+edited copy in a temporary directory and loaded through a second instance of
+the oracle's Python module: a dropped dagger, a wrong staggered phase, a lost
+factor 1/2, a boundary factor on the wrong link, a wrong power in the
+shifted recurrence. Mistakes in Algorithm 1 (the oracle's numpy code) run
+from an edited copy of that module: a dropped term, transposed operands, a
+missing conjugate, factors in the wrong order.
 """
 import importlib.util
 import os
@@ -112,6 +114,63 @@ def mscg_error(mod):
 
 CHECKS = {"spectrum": (spectrum_error, 1e-12), "antihermitian": (antihermitian_error, 1e-13),
           "mscg": (mscg_error, 1e-10)}
+
+# mistakes in Algorithm 1 as the oracle's numpy code writes it (oracle.py)
+ALG1_MUTANTS = {
+    "(1 - beta) term dropped from the beta recurrence":
+        ("+ t @ (eye - beta_s[s]) @ np.conj(rho_prev).T)", "+ t @ np.conj(rho_prev).T)"),
+    "operands of the shifted direction update transposed":
+        ("P[s] = Q + P[s] @ beta_new @ np.conj(rho).T", "P[s] = Q + P[s] @ np.conj(rho).T @ beta_new"),
+    "conjugate dropped in the unshifted direction update":
+        ("P[0] = Q + P[0] @ np.conj(rho).T", "P[0] = Q + P[0] @ rho.T"),
+    "alpha^(s) factors in the wrong order":
+        ("alpha_new = beta_new @ t @ alpha_s[s]", "alpha_new = t @ beta_new @ alpha_s[s]"),
+    "alpha_k^-1 dropped from the shifted residual coefficients":
+        ("delta_s[s] = rho @ ainv @ alpha_new", "delta_s[s] = rho @ alpha_new"),
+}
+
+
+def _alg1_mutant(old, new):
+    path = os.path.join(ROOT, "oracle", "oracle.py")
+    src = open(path).read()
+    assert src.count(old) == 1, old
+    spec = importlib.util.spec_from_file_location("oracle_alg1_mutant", path)
+    mod = importlib.util.module_from_spec(spec)
+    exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
+    return mod
+
+
+def alg1_error(mod):
+    """The two pins of Algorithm 1 on a small lattice: the converged solutions
+    against dense solves (the plain definition), and the shifted residual
+    B - (A + s) X^(s) against Q_k delta^(s)_k after a fixed number of steps."""
+    dims, bc = (2, 2, 2, 4), (1, 1, 1, -1)
+    r = configs.workload_coefficients("c2")
+    U = random_gauge(dims, 0.7, 21)
+    B = gaussian_block(dims, 2, 22)
+    m, err = 0.1, 0.0
+    out = mod.sbcgrq_lattice(dims, bc, U, m, r.beta, B, 1e-12, maxiter=200)
+    for s, sig in enumerate(r.beta):
+        A = O.dense_operator(dims, bc, U, m, sig)
+        xd = np.linalg.solve(A, B.reshape(-1, B.shape[2])).reshape(B.shape)
+        err = max(err, float(np.linalg.norm(out["X"][s] - xd) / np.linalg.norm(xd)))
+    out = mod.sbcgrq_lattice(dims, bc, U, m, r.beta, B, 0.0, maxiter=7, freeze_tol=0.0)
+    Q = out["Q"].reshape(B.shape)
+    for s, sig in enumerate(r.beta):
+        R = B - O.mdagm(dims, bc, U, m, sig, out["X"][s])
+        Rq = np.einsum("vcj,ji->vci", Q, out["delta_s"][s])
+        err = max(err, float(np.abs(R - Rq).max() / np.abs(B).max()))
+    return err
+
+
+def test_algorithm1_pins_pass_on_the_oracle():
+    assert alg1_error(O) < 1e-9
+
+
+@pytest.mark.parametrize("name", sorted(ALG1_MUTANTS))
+def test_planted_algorithm1_mistake_is_caught(name):
+    old, new = ALG1_MUTANTS[name]
+    assert alg1_error(_alg1_mutant(old, new)) > 1e-6, name
 
 
 def test_pins_pass_on_the_oracle():
