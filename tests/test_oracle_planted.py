@@ -6,7 +6,8 @@ the C operator and multi-shift CG (oracle/staggered.c) are compiled from an
 edited copy in a temporary directory and loaded through a second instance of
 the oracle's Python module: a dropped dagger, a wrong staggered phase, a lost
 factor 1/2, a boundary factor on the wrong link, a wrong power in the
-shifted recurrence. Mistakes in Algorithm 1 (the oracle's numpy code) run
+shifted recurrence, and in the force a lost sign, phase or boundary factor,
+a conjugate on the wrong factor, a transposed gradient. Mistakes in Algorithm 1 (the oracle's numpy code) run
 from an edited copy of that module: a dropped term, transposed operands, a
 missing conjugate, factors in the wrong order.
 """
@@ -37,6 +38,16 @@ MUTANTS = {
          "acc[a] = c_sub(acc[a], c_scale(t, e * bf));", "spectrum"),
     "shifted direction update with zeta ratio to the first power":
         ("double bs = beta * ratio * ratio;", "double bs = beta * ratio;", "mscg"),
+    "force: sign of the odd-site links dropped":
+        ("          f = -f;\n", "", "force"),
+    "force: staggered phase dropped":
+        ("double f = eta(c, mu) * bf * coef[v];", "double f = bf * coef[v];", "force"),
+    "force: boundary factor dropped":
+        ("double f = eta(c, mu) * bf * coef[v];", "double f = eta(c, mu) * coef[v];", "force"),
+    "force: conjugate on the wrong factor of the outer product":
+        ("cplx t = c_cjmul(row[bb], col[a]);", "cplx t = c_cjmul(col[a], row[bb]);", "force"),
+    "force: gradient transposed":
+        ("cplx t = m[l * 9 + 3 * bb + a];", "cplx t = m[l * 9 + 3 * a + bb];", "force"),
 }
 
 
@@ -112,8 +123,40 @@ def mscg_error(mod):
     return err
 
 
+def force_error(mod):
+    """The force's finite-difference pin: the derivative of the action along
+    random complex directions of a few links (one of them crossing the
+    antiperiodic t boundary) against Re Tr[dU^dag G]."""
+    dims, bc = (4, 4, 2, 4), (1, 1, 1, -1)
+    r = configs.workload_coefficients("c1")
+    U = random_gauge(dims, 0.5, 7)
+    B = gaussian_block(dims, 2, 8)
+    m = 0.1
+
+    def S(Uv):
+        X, _ = O.solve_block(dims, bc, Uv, m, r.beta, B, 1e-14)
+        return O.action(B, X, r.a0, r.alpha).sum()
+
+    X, _ = O.solve_block(dims, bc, U, m, r.beta, B, 1e-14)
+    G = mod.force(dims, bc, U, r.alpha, X)
+    V = int(np.prod(dims))
+    t_edge = 2 + 4 * (1 + 4 * (0 + 2 * 3))  # site (2, 1, 0, 3): its t link crosses the boundary
+    links = [(3, t_edge), (0, 5), (1, 17), (2, 40), (3, 9), (0, V - 1)]
+    rng = np.random.default_rng(1)
+    eps, err = 1e-5, 0.0
+    for mu, idx in links:
+        dU = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+        Up, Um = U.copy(), U.copy()
+        Up[mu, idx] += eps * dU
+        Um[mu, idx] -= eps * dU
+        fd = (S(Up) - S(Um)) / (2 * eps)
+        an = np.real(np.sum(dU * np.conj(G[mu, idx])))
+        err = max(err, abs(fd - an) / max(1.0, abs(an)))
+    return err
+
+
 CHECKS = {"spectrum": (spectrum_error, 1e-12), "antihermitian": (antihermitian_error, 1e-13),
-          "mscg": (mscg_error, 1e-10)}
+          "mscg": (mscg_error, 1e-10), "force": (force_error, 1e-6)}
 
 # mistakes in Algorithm 1 as the oracle's numpy code writes it (oracle.py)
 ALG1_MUTANTS = {
@@ -183,4 +226,4 @@ def test_planted_mistake_is_caught(tmp_path, name):
     old, new, pin = MUTANTS[name]
     mod = _mutant(tmp_path, old, new)
     check, tol = CHECKS[pin]
-    assert check(mod) > 1e3 * tol, name
+    assert check(mod) > 100 * tol, name
