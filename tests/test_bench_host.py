@@ -35,3 +35,24 @@ def test_stored_traffic_follows_the_source(tmp_path, monkeypatch):
     assert bench.stored_traffic("c5", "mixed", "hop") is None       # no entry for it
     kernel.write_text("// kernel v2\n")                               # source changed
     assert bench.stored_traffic("c5", "mixed", "update") is None
+
+
+def test_cpu_baseline_leg_on_a_small_workload():
+    """The cpu_baseline leg (the oracle's multi-shift CG timed on the host and
+    scaled to a per-vector solve) at 8^4 with a short budget: the contract's
+    fields and the thread count it reports."""
+    import re
+
+    from paper_1808_01829_amd.inputs import configs, gaussian_block, random_gauge
+    w = dict(configs.WORKLOADS["c2"])
+    r = configs.workload_coefficients("c2")
+    U = random_gauge(w["dims"], w["eps"], 2000)
+    B = gaussian_block(w["dims"], w["n"], 2001)
+    try:
+        out = bench.cpu_oracle_sample(U, B, w, r, 500, 0.2, threads=2)
+    finally:
+        bench.set_omp_threads(os.cpu_count() or 1)
+    assert out["kind"] == "oracle" and out["unit"] == "RHS-solves/s" and out["cores"] == 2
+    assert out["value"] > 0
+    assert re.search(r"[0-9.]+ s/iteration", out["sample"])
+    assert "scaled to the 500 iterations" in out["sample"]
