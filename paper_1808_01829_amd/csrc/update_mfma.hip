@@ -91,7 +91,7 @@ __device__ __forceinline__ void bload(const F* B, int lane, F (&b)[MfShape<N>::K
 }
 
 // The shift coefficients are kept in LDS as the complex n x n matrix, (re,
-// im) pairs, a quarter of the expanded form; each lane forms its B-operand
+// im) pairs, half of the expanded form; each lane forms its B-operand
 // reals from it: B[2k][j] = Re M[k][j], B[2k][n+j] = Im, B[2k+1][j] = -Im,
 // B[2k+1][n+j] = Re, at kk = g*KS + ks, flat = nt*16 + c.
 // d += a * B(M), the B operands read from LDS one k-step at a time (few
