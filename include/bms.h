@@ -91,13 +91,24 @@ typedef struct bms_opts {
                              <= tol, or >= 1: FP32 from the start */
 } bms_opts;
 
-/* Solver statistics (filled on BMS_OK, BMS_ENOCONV and BMS_EBREAKDOWN). */
+/* Solver statistics (filled on BMS_OK, BMS_ENOCONV and BMS_EBREAKDOWN). Every
+   block iteration of the solve is counted once, in whichever phase ran it:
+   iterations = multishift_iterations + refine_iterations
+              = iterations_f64 + iterations_f32. */
 typedef struct bms_stats {
-  int iterations;          /* block iterations of the multi-shift solve */
-  int hop_calls;           /* half-hop applications of n-wide (or wider) blocks */
-  int reliable_updates;    /* MIXED: FP64 residual replacements */
-  int refine_iterations;   /* MIXED: block iterations after the first phase (the FP32
-                              multi-shift phase and the defect correction) */
+  int iterations;          /* block iterations of every phase */
+  int multishift_iterations; /* of these, the first block multi-shift loop on B
+                              (Algorithm 1; in MIXED the FP64 phase down to
+                              mixed_switch) */
+  int refine_iterations;   /* the iterations after it: the FP32 multi-shift phase
+                              (MIXED), an FP64 restart after a diverged FP32 loop,
+                              and the per-shift defect correction */
+  int iterations_f64;      /* block iterations on FP64 blocks */
+  int iterations_f32;      /* block iterations on FP32 blocks */
+  int hop_calls;           /* half hops that did work: two per block iteration, two
+                              per reliable update, two per shift of each true-residual
+                              check or residual formation */
+  int reliable_updates;    /* MIXED: FP64 residual replacements that ran */
   int converged;           /* 1 if every shift and column met tol (true FP64 residual) */
   double max_true_residual;/* max over shifts and columns of |b - (A+s)x| / |b| */
   double* true_residual;   /* optional caller array [n_shifts][n]; NULL to skip */

@@ -54,10 +54,23 @@ class bms_opts(ctypes.Structure):
 
 
 class bms_stats(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int), ("hop_calls", ctypes.c_int),
-                ("reliable_updates", ctypes.c_int), ("refine_iterations", ctypes.c_int),
-                ("converged", ctypes.c_int), ("max_true_residual", ctypes.c_double),
+    _fields_ = [("iterations", ctypes.c_int), ("multishift_iterations", ctypes.c_int),
+                ("refine_iterations", ctypes.c_int), ("iterations_f64", ctypes.c_int),
+                ("iterations_f32", ctypes.c_int), ("hop_calls", ctypes.c_int),
+                ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
+                ("max_true_residual", ctypes.c_double),
                 ("true_residual", ctypes.POINTER(ctypes.c_double))]
+
+
+_STAT_INTS = ("iterations", "multishift_iterations", "refine_iterations", "iterations_f64",
+              "iterations_f32", "hop_calls", "reliable_updates")
+
+
+def _stats_dict(st):
+    d = {k: getattr(st, k) for k in _STAT_INTS}
+    d["converged"] = bool(st.converged)
+    d["max_true_residual"] = st.max_true_residual
+    return d
 
 
 class BmsError(RuntimeError):
@@ -188,9 +201,8 @@ def bms_solve(ctx, mass, n, shifts, tol, max_iter, opts, B, X, want_residuals=Tr
     rc = _lib().bms_solve(ctx, float(mass), int(n), ns, _doubles(shifts), float(tol),
                           int(max_iter), ctypes.byref(opts) if opts is not None else None,
                           _ptr(B), _ptr(X), ctypes.byref(st))
-    stats = dict(iterations=st.iterations, hop_calls=st.hop_calls,
-                 reliable_updates=st.reliable_updates, refine_iterations=st.refine_iterations,
-                 converged=bool(st.converged), max_true_residual=st.max_true_residual, status=rc)
+    stats = _stats_dict(st)
+    stats["status"] = rc
     if res is not None:
         stats["true_residual"] = [[res[s * n + i] for i in range(n)] for s in range(ns)]
     if raise_on_error:
@@ -254,10 +266,10 @@ def bms_solve_batch(ctxs, masses, ns, shifts, tols, max_iters, opts, Bs, Xs, rai
     stats = []
     for i in range(k):
         nsh, n = len(shifts[i]), ns[i]
-        stats.append(dict(iterations=st[i].iterations, refine_iterations=st[i].refine_iterations,
-                          reliable_updates=st[i].reliable_updates, converged=bool(st[i].converged),
-                          max_true_residual=st[i].max_true_residual, status=status[i],
-                          true_residual=[[res[i][s * n + j] for j in range(n)] for s in range(nsh)]))
+        d = _stats_dict(st[i])
+        d["status"] = status[i]
+        d["true_residual"] = [[res[i][s * n + j] for j in range(n)] for s in range(nsh)]
+        stats.append(d)
     if raise_on_error and rc != 0:
         bad = next(i for i in range(k) if status[i] != 0)
         _check(ctxs[bad], status[bad])

@@ -102,6 +102,17 @@ extern "C" int bms_solve_batch(int nprob, bms_ctx* const* ctxs, const double* ma
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return BMS_EINVAL;  // a context serves one solve at a time
   }
+  // All workspace first, one context after another: a solve that grew a
+  // buffer inside a thread would free and allocate device memory while a
+  // sibling thread captures its iteration chunk into a hipGraph.
+  for (int i = 0; i < nprob; ++i) {
+    int rc = solve_reserve(ctxs[i], mass[i], n[i], n_shifts[i], shifts[i], tol[i], max_iter[i],
+                           opts ? &opts[i] : nullptr, B[i], X[i]);
+    if (rc) {
+      for (int j = 0; j < nprob; ++j) status[j] = j == i ? rc : BMS_OK;
+      return rc;
+    }
+  }
   std::vector<std::thread> th;
   th.reserve(nprob);
   for (int i = 0; i < nprob; ++i)

@@ -154,7 +154,7 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   if ((rc = stream_begin(c))) return rc;
   size_t blk = (size_t)c->vh * 3 * n;
   void* Y;
-  if ((rc = scratch_buf(c, 20, blk * ns * sizeof(double2), &Y))) return rc;
+  if ((rc = scratch_buf(c, S_Y, blk * ns * sizeof(double2), &Y))) return rc;
   for (int s = 0; s < ns; ++s)
     HIP_TRY(c, launch_hop<double>(c, 1, n, (const double2*)X + s * blk, (double2*)Y + s * blk,
                                   nullptr, 0.0, 1.0, nullptr));

@@ -12,6 +12,35 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Workspace slots of a context (bms_ctx::scratch), one device buffer each,
+// grown on first use of a larger shape and reused.
+enum Slot {
+  S_TMP = 0,  // odd-site temporary of bms_apply_mdagm
+  S_W1,       // D_oe P^(0) (odd sites)
+  S_W,        // (A + s0) P^(0)
+  S_Q,        // orthonormal residual block Q_k
+  S_P,        // directions P^(s), two buffers per shift for the two-iteration update
+  S_X,        // solutions X^(s) in the block precision
+  S_SMALL,    // n x n FP64 state of the recurrences
+  S_PART,     // partial sums of the grid reductions
+  S_M,        // per-shift coefficient matrices of the update
+  S_FLAGS,    // SolverFlags and the small-step arrival counter
+  S_RES,      // residual norms, action sums, n x n Grams read back by the host
+  S_LOG,      // per-iteration traffic log of the update
+  S_R1,       // FP64 odd temporary
+  S_R2,       // FP64 even temporary
+  S_R0,       // FP64 true residual (reliable update)
+  S_RB,       // FP64 defect-correction right-hand side
+  S_E,        // FP64 defect-correction solution
+  S_COLS,     // per-column scale factors
+  S_RBC,      // one column of S_RB
+  S_EC,       // its correction
+  S_E2,       // FP64 solutions of the FP32 multi-shift phase
+  S_CMAT,     // n x n FP64 coefficient matrix
+  S_Y,        // bms_force: Y = D_oe X of every shift (odd sites)
+  S_COUNT
+};
+
 // Device-side solver control block (all written by kernels, read by the host
 // between graph chunks).
 struct SolverFlags {
@@ -25,6 +54,7 @@ struct SolverFlags {
   int diverged;       // the true residual grew or stalled over reliable updates (soft stop)
   int rel_stall;      // reliable updates in a row without progress of the true residual
   int upd_done;       // `iter` as seen by the last matrix-core update that ran (-1: none)
+  int rel_count;      // reliable updates that ran (not skipped after a stop)
   int active[BMS_MAX_SHIFTS];  // shift still updated
   int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
   double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift
@@ -76,6 +106,8 @@ struct bms_ctx {
   // graph cache for the iteration chunk
   hipGraphExec_t graph_exec = nullptr;
   std::string graph_key;
+  // work done by the current bms_solve (reset at its start, reported in bms_stats)
+  long it_f64 = 0, it_f32 = 0, hop_work = 0, rel_work = 0;
 };
 
 // error helpers
@@ -93,6 +125,9 @@ int ensure_device(bms_ctx* c);
 int ensure_buf(bms_ctx* c, DevBuf& b, size_t bytes);
 int scratch_buf(bms_ctx* c, int slot, size_t bytes, void** p);
 int stream_begin(bms_ctx* c);
+// size every workspace slot a solve of this shape may use (see solver.cpp)
+int solve_reserve(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
+                  int max_iter, const bms_opts* opts, const void* B, const void* X);
 int stream_end(bms_ctx* c);
 
 // ---- launchers (all enqueue on c->stream) ---------------------------------

@@ -206,6 +206,7 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
     fl->iter = 0;
     fl->need_explicit = 0;
     fl->upd_done = -1;
+    fl->rel_count = 0;
     *s.counter = 0;
   }
   if (pass == 0)
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
     }
     return;
   }
+  if (threadIdx.x == 0) fl->rel_count += 1;
   sm_load(L0, Gin, n);
   int st = sm_chol_upper(L1, L0, n, p.breakdown_tol);
   if (st) {

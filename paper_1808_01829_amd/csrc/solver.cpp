@@ -30,32 +30,6 @@
 
 namespace {
 
-enum Slot {
-  S_TMP = 0,  // used by bms_apply_mdagm
-  S_W1,
-  S_W,
-  S_Q,
-  S_P,
-  S_X,
-  S_SMALL,
-  S_PART,
-  S_M,
-  S_FLAGS,
-  S_RES,
-  S_LOG,
-  S_R1,    // FP64 odd temporary
-  S_R2,    // FP64 even temporary
-  S_R0,    // FP64 true residual (reliable update)
-  S_RB,    // FP64 defect-correction right-hand side
-  S_E,     // FP64 defect-correction solution
-  S_COLS,  // per-column scale factors
-  S_RBC,   // one column of S_RB
-  S_EC,    // its correction
-  S_E2,    // FP64 solutions of the FP32 multi-shift phase
-  S_CMAT,  // n x n FP64 coefficient matrix
-  S_COUNT
-};
-
 const double kEps = 2.220446049250313e-16;
 const double kEps32 = 1.1920928955078125e-07;
 // the solver flags, then the arrival counter of the small-step blocks
@@ -171,6 +145,9 @@ UpdateArgs<T, T> update_args(const Work& w) {
   return ua;
 }
 
+// ev: NULL, or 8 timing events recorded around the 7 launches (direct
+// launches only: event-record nodes of a replayed graph carry no usable
+// timestamps on this runtime, measured).
 template <typename T>
 int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
                       hipEvent_t* ev) {
@@ -289,8 +266,8 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
 }
 
 // Enqueue K iterations: replayed from a captured hipGraph when allowed (the
-// chunk holds kernel launches only), else launched directly (with per-kernel
-// events when timing).
+// chunk holds kernel launches only), else launched directly (always while
+// per-kernel timing is on, with events between the kernels).
 template <typename T>
 int enqueue_chunk(bms_ctx* c, const Work& w, const SmallParams& sp, double mass, int K,
                   bool use_graph) {
@@ -311,7 +288,8 @@ int enqueue_chunk(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
     c->graph_key.clear();
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = BMS_OK;
-    for (int k = 0; k < K && rc == BMS_OK; ++k) rc = enqueue_iteration<T>(c, w, sp, mass, nullptr);
+    for (int k = 0; k < K && rc == BMS_OK; ++k)
+      rc = enqueue_iteration<T>(c, w, sp, mass, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rc) {
@@ -380,7 +358,6 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
     if (mixed && enqueued + K - last_rel >= o.reliable_interval) {
       if ((rc = enqueue_reliable(c, w, sp, mass, B, Xout, xmap, R1, R2, R0, false))) return rc;
       last_rel = enqueued + K;
-      cr.reliable++;
     }
     HIP_TRY(c, hipMemcpyAsync(&hf, w.flags, sizeof hf, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -426,7 +403,10 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
                                 c->stream));
   }
   cr.iters = hf.iter;
+  cr.reliable = hf.rel_count;
   cr.diverged = hf.diverged != 0;
+  (mixed ? c->it_f32 : c->it_f64) += hf.iter;
+  c->hop_work += 2L * hf.iter + 2L * hf.rel_count;
   // A breakdown or non-finite value inside the iteration stops it with the
   // last finite iterate in X (the update of that step is skipped); the true
   // residual check and defect correction then decide. Only a failure of the
@@ -437,6 +417,69 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
 }
 
 }  // namespace
+
+// Size every workspace slot that a solve of n columns, ns shifts and max_iter
+// iterations can touch, in any phase and precision (FP64 blocks are the
+// larger), and the event pool of per-kernel timing. Called serially for each
+// context before bms_solve_batch starts its threads, so that no solve grows a
+// buffer (hipFree, hipMalloc, hipMemset) while another captures a graph.
+static int validate_solve(bms_ctx* c, double mass, int n, int ns, const double* shifts,
+                          double tol, int max_iter, const bms_opts* o, const void* B,
+                          const void* X);
+
+int solve_reserve(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
+                  int max_iter, const bms_opts* opts, const void* B, const void* X) {
+  // a call that bms_solve rejects on the host reserves nothing (and reports
+  // its error from bms_solve)
+  if (validate_solve(c, mass, n, ns, shifts, tol, max_iter, opts, B, X) != BMS_OK) {
+    c->last_error.clear();
+    return BMS_OK;
+  }
+  bms_opts o;
+  bms_default_opts(&o);
+  if (opts) o = *opts;
+  const int check_interval = o.check_interval;
+  int rc;
+  if ((rc = ensure_device(c))) return rc;
+  const size_t rows = (size_t)3 * c->vh, blk = rows * n, nn = (size_t)n * n, e = sizeof(double2);
+  void* p;
+  const struct {
+    int slot;
+    size_t bytes;
+  } need[] = {
+      {S_W1, blk * e},
+      {S_W, blk * e},
+      {S_Q, blk * e},
+      {S_P, blk * e * ns * 2},
+      {S_X, blk * e * ns},
+      {S_SMALL, (17 * nn + 2 * ns * nn + n + 1) * e + 64},
+      {S_PART, std::max(part_bytes(gram_blocks((int)rows, n, c->num_cu), 4 * (int)nn),
+                        part_bytes(gram_blocks((int)rows, 1, c->num_cu), 4))},
+      {S_M, 3 * ns * nn * e},
+      {S_FLAGS, kFlagsBytes},
+      {S_LOG, (size_t)max_iter * sizeof(int) + 64},
+      {S_R1, blk * e},
+      {S_R2, blk * e},
+      {S_R0, blk * e},
+      {S_RES, std::max({(size_t)ns * n * e, 2 * nn * e, (size_t)(n + BMS_MAX_SHIFTS) * e}) + 64},
+      {S_RB, blk * e},
+      {S_E, blk * e},
+      {S_COLS, 3 * n * sizeof(double) + 64},
+      {S_RBC, rows * e},
+      {S_EC, rows * e},
+      {S_E2, (size_t)ns * blk * e},
+      {S_CMAT, nn * e + 64},
+  };
+  for (const auto& q : need)
+    if ((rc = scratch_buf(c, q.slot, q.bytes, &p))) return rc;
+  if (c->timing && (int)c->evpool.size() < 8 * check_interval) {
+    size_t old = c->evpool.size();
+    c->evpool.resize(8 * check_interval);
+    for (size_t i = old; i < c->evpool.size(); ++i) HIP_TRY(c, hipEventCreate(&c->evpool[i]));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return BMS_OK;
+}
 
 // Per shift s and column i of user-ordered solutions: rn2[s][i] = |b_i - (A+s)x_i|^2
 // and bn2[i] = |b_i|^2.
@@ -460,6 +503,7 @@ static int residual_norms(bms_ctx* c, double mass, int n, int ns, const double* 
     HIP_TRY(c, launch_resid_norms(c->stream, rows, n, B, t2, (double2*)out + (size_t)s * n,
                                   (double2*)pp, nb));
   }
+  c->hop_work += 2L * ns;
   std::vector<double2> h((size_t)ns * n);
   HIP_TRY(c, hipMemcpyAsync(h.data(), out, h.size() * sizeof(double2), hipMemcpyDeviceToHost,
                             c->stream));
@@ -616,6 +660,7 @@ static int mixed_phase2(bms_ctx* c, double mass, int n, int ns, const double* sh
     const double2* xs = (const double2*)X + (size_t)s * blk;
     HIP_TRY(c, launch_hop<double>(c, 1, n, xs, t1, nullptr, 0.0, 1.0, nullptr));
     HIP_TRY(c, launch_hop<double>(c, 0, n, t1, t2, xs, mass * mass + shifts[s], -1.0, nullptr));
+    c->hop_work += 2;
     return BMS_OK;
   };
   if ((rc = apply_a(s0))) return rc;
@@ -689,22 +734,26 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
   for (int s = 0; s < ns; ++s) sig[s] = shifts[order[s]];
   CoreResult cr;
   int refine_iters = 0, reliable = 0;
+  c->it_f64 = c->it_f32 = c->hop_work = c->rel_work = 0;
   // MIXED: an FP64 block multi-shift phase down to the switch residual (every
   // shift kept updated until the final tolerance), then the FP32 phase
   const bool two_phase = sizeof(T) == 4 && o.mixed_switch > tol && o.mixed_switch < 1.0;
+  int first_iters = 0;
   if (two_phase) {
     bms_opts o1 = o;
     o1.freeze_tol = o.freeze_tol > 0 ? std::min(o.freeze_tol, 0.5 * tol) : 0.5 * tol;
     if ((rc = solve_core<double>(c, mass, n, ns, sig.data(), order.data(), o.mixed_switch,
                                  max_iter, o1, B, X, cr)))
       return rc;
+    first_iters = cr.iters;
     if (!cr.error &&
         (rc = mixed_phase2(c, mass, n, ns, shifts, order.data(), tol, max_iter, o, B, X,
                            refine_iters, reliable)))
       return rc;
-  } else if ((rc = solve_core<T>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X,
-                                 cr))) {
-    return rc;
+  } else {
+    if ((rc = solve_core<T>(c, mass, n, ns, sig.data(), order.data(), tol, max_iter, o, B, X, cr)))
+      return rc;
+    first_iters = cr.iters;
   }
   reliable += cr.reliable;
   bool fell_back = false;
@@ -767,6 +816,7 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
                                 c->stream));
       HIP_TRY(c, launch_hop<double>(c, 1, n, xs, t1, nullptr, 0.0, 1.0, nullptr));
       HIP_TRY(c, launch_hop<double>(c, 0, n, t1, t2, xs, mass * mass + shifts[s], -1.0, nullptr));
+      c->hop_work += 2;
       HIP_TRY(c, launch_resid_block(c->stream, rows, n, B, t2, (const double*)cols,
                                     (const double*)cols + n, RB, nullptr));
       double tin = 0.5 * tol / worst;
@@ -842,10 +892,14 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
       mx = std::max(mx, std::isfinite(r) ? r : 1e300);
     }
   if (st) {
-    st->iterations = cr.iters;
-    st->hop_calls = 2 * (cr.iters + refine_iters) + 2 * ns;
+    const long total = c->it_f64 + c->it_f32;
+    st->iterations = (int)total;
+    st->multishift_iterations = first_iters;
+    st->refine_iterations = (int)(total - first_iters);
+    st->iterations_f64 = (int)c->it_f64;
+    st->iterations_f32 = (int)c->it_f32;
+    st->hop_calls = (int)c->hop_work;
     st->reliable_updates = reliable;
-    st->refine_iterations = refine_iters;
     st->converged = mx <= tol;
     st->max_true_residual = mx;
     if (st->true_residual) memcpy(st->true_residual, res.data(), res.size() * sizeof(double));

@@ -37,13 +37,21 @@ def test_graph_replay_matches_direct_launches(torch, prec):
     runs = [(r.beta, 1e-10, 300), (r.beta[:5], 1e-8, 37), (r.beta, 1e-10, 300)]
     for shifts, tol, mi in runs:
         res = {}
-        for g in (0, 1, 1, 0, 1):
+        # (use_graph, per-kernel timing): with timing on, chunks launch directly
+        for g, tm in ((0, 0), (1, 0), (1, 1), (0, 1), (1, 0), (1, 1)):
+            ctx.timing(bool(tm))
             X, st = ctx.solve(0.05, shifts, Bd, tol=tol, max_iter=mi, precision=p, use_graph=g,
                               raise_on_error=False)
             torch.cuda.synchronize()
+            if tm:
+                kt = ctx.timing_read()
+                # every block iteration of every phase is timed: two half hops each
+                assert kt["hop"][1] == 2 * st["iterations"]
+                assert kt["hop"][0] > 0 and kt["update"][0] > 0
             _ = (Bd * 2).sum().item()  # eager work between replays
-            res.setdefault(g, []).append((to_np(X), st["iterations"]))
-        ref, it = res[0][0]
+            res.setdefault((g, tm), []).append((to_np(X), st["iterations"]))
+        ctx.timing(False)
+        ref, it = res[(0, 0)][0]
         for g, lst in res.items():
             for X, its in lst:
                 assert its == it
@@ -83,6 +91,34 @@ def test_uneven_batch_equals_individual_solves(torch):
     for i, (dims, n, seed) in enumerate(probs):
         assert stats[i]["status"] == 0 and stats[i]["converged"]
         X1, st1 = ctxs[i].solve(0.05, shifts[i], Bs[i], tol=1e-10)
+        assert st1["iterations"] == stats[i]["iterations"]
+        assert np.array_equal(to_np(X1), to_np(Xs[i]))
+        tr = O.true_residuals(dims, BC, Us[i], 0.05, shifts[i], to_np(Bs[i]), to_np(Xs[i]))
+        assert tr.max() <= 1e-10
+
+
+def test_uneven_batch_mixed_precision(torch):
+    """The benchmark's kind of batch: mixed precision, three lattices of
+    different volume, one context each. Each problem equals its own solve
+    (bit for bit) and meets tol in the oracle's true residual."""
+    from paper_1808_01829_amd import bms
+    r = configs.workload_coefficients("c2")
+    probs = [((4, 4, 4, 4), 8, 71), ((8, 8, 8, 8), 8, 73), ((6, 6, 6, 6), 16, 75)]
+    ctxs, Us, Bs = [], [], []
+    for dims, n, seed in probs:
+        c, U, B = _problem(torch, dims, n, seed)
+        ctxs.append(c)
+        Us.append(U)
+        Bs.append(to_dev(torch, B))
+    o = bms.bms_default_opts()
+    o.precision = bms.BMS_PREC_MIXED
+    o.reliable_interval = 50
+    shifts = [r.beta] * 3
+    Xs, stats = bms.solve_batch(ctxs, [0.05] * 3, shifts, Bs, tol=1e-10, opts=o)
+    for i, (dims, n, seed) in enumerate(probs):
+        assert stats[i]["status"] == 0 and stats[i]["converged"]
+        assert stats[i]["iterations_f32"] > 0
+        X1, st1 = ctxs[i].solve(0.05, shifts[i], Bs[i], tol=1e-10, opts=o)
         assert st1["iterations"] == stats[i]["iterations"]
         assert np.array_equal(to_np(X1), to_np(Xs[i]))
         tr = O.true_residuals(dims, BC, Us[i], 0.05, shifts[i], to_np(Bs[i]), to_np(Xs[i]))

@@ -25,8 +25,12 @@ def torch():
     return torch_gpu()
 
 
+# block widths 2 ... 16 (the workloads' widths 8 and 16 with the 16 poles of
+# the 16^3 x 32 force workload), odd widths, and a lattice with extent 2
 @pytest.mark.parametrize("dims,n,name", [((4, 4, 2, 4), 2, "c1"), ((4, 4, 4, 6), 3, "c2"),
-                                         ((8, 8, 8, 8), 4, "c2")])
+                                         ((8, 8, 8, 8), 4, "c2"), ((4, 4, 4, 6), 8, "c4"),
+                                         ((4, 6, 4, 4), 16, "c4"), ((6, 4, 2, 4), 5, "c4"),
+                                         ((4, 4, 4, 4), 12, "c2")])
 def test_force_parity(torch, dims, n, name):
     from paper_1808_01829_amd import bms
     r = configs.workload_coefficients(name)

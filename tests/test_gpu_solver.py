@@ -2,11 +2,13 @@
 
 P1 (hard): every column of every shift has true FP64 relative residual
            |b - (A + s) x| / |b| <= tol, recomputed here with the oracle operator.
-P2:        X^(s) within rtol of the oracle's multi-shift CG solution at 1e-13;
-           the GPU runs at tol 1e-12 so that the difference is set by the
-           conditioning bound kappa_s * 1e-12 (kappa_s <= (16+m^2+s)/(m^2+s)).
-P3:        FP64 iteration count within +-2 of the oracle's Algorithm 1 (both
-           stopping when every residual estimate is below tol/2).
+P2:        |X^(s) - X_ora^(s)|_F / |X_ora^(s)|_F <= 1e-9 for every shift, flat,
+           against the oracle's multi-shift CG solution at 1e-14 (whose own
+           error is below 1e-10 on these workloads); asserted with the GPU at
+           tol 1e-12 and at the workloads' tol 1e-10, each shift's value printed.
+P3:        FP64 iteration count of the block multi-shift loop within +-2 of
+           the oracle's Algorithm 1 (both stopping when every residual
+           estimate is below tol/2).
 """
 import numpy as np
 import pytest
@@ -42,9 +44,22 @@ def _ctx(torch, dims, U, bc=BC):
     return c
 
 
-def _kappa(mass, shifts):
-    m2 = mass * mass
-    return (16 + m2 + np.asarray(shifts)) / (m2 + np.asarray(shifts))
+P2_RTOL = 1e-9
+
+
+def _p2(X, Xo, label):
+    """Per-shift relative Frobenius difference; printed, and returned."""
+    e = np.array([np.linalg.norm(X[s] - Xo[s]) / np.linalg.norm(Xo[s]) for s in range(len(X))])
+    print("P2 %s: max %.2e (margin %.0fx below %.0e); per shift %s" % (
+        label, e.max(), P2_RTOL / max(e.max(), 1e-300), P2_RTOL,
+        " ".join("%.1e" % v for v in e)))
+    return e
+
+
+def _check_stats(st):
+    assert st["iterations"] == st["multishift_iterations"] + st["refine_iterations"]
+    assert st["iterations"] == st["iterations_f64"] + st["iterations_f32"]
+    assert st["hop_calls"] >= 2 * st["iterations"]
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
@@ -53,34 +68,38 @@ def test_solver_parity_f64(torch, name):
     c = _ctx(torch, dims, U)
     X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-12, max_iter=5000)
     X = to_np(X)
+    _check_stats(st)
+    assert st["iterations_f32"] == 0
     # P1 with the oracle operator
     tr = O.true_residuals(dims, BC, U, m, r.beta, B, X)
     assert tr.max() <= 1e-12
     assert abs(st["max_true_residual"] - tr.max()) <= 1e-3 * tr.max() + 1e-16
-    # P2
-    Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-13)
-    for s in range(len(r.beta)):
-        bound = max(1e-9, 5 * _kappa(m, r.beta[s]) * 1e-12)
-        assert np.linalg.norm(X[s] - Xo[s]) <= bound * np.linalg.norm(Xo[s])
+    # P2, flat
+    Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-14)
+    assert _p2(X, Xo, "%s tol 1e-12" % name).max() <= P2_RTOL
     # P3: the solver stops when every estimate is below tol/2
     oo = O.sbcgrq_lattice(dims, BC, U, m, r.beta, B, 0.5e-12)
-    assert abs(st["iterations"] - oo["iters"]) <= 2
+    assert abs(st["multishift_iterations"] - oo["iters"]) <= 2
 
 
-def test_solver_tol_1e10_and_action(torch):
-    dims, n, U, B, m, r = _setup("c2")
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_solver_tol_1e10_and_action(torch, name):
+    dims, n, U, B, m, r = _setup(name)
     c = _ctx(torch, dims, U)
     Bd = to_dev(torch, B)
     X, st = c.solve(m, r.beta, Bd, tol=1e-10)
     X = to_np(X)
+    _check_stats(st)
     assert st["converged"] and st["max_true_residual"] <= 1e-10
     tr = O.true_residuals(dims, BC, U, m, r.beta, B, X)
     assert tr.max() <= 1e-10
+    # P2 at the workload's own tolerance, flat per shift
+    Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-14)
+    assert _p2(X, Xo, "%s tol 1e-10" % name).max() <= P2_RTOL
     S = c.action(r.a0, r.alpha, Bd, to_dev(torch, X))
     So = O.action(B, X, r.a0, r.alpha)
     assert np.allclose(S, So, rtol=1e-12)
-    # the action is quadratic in the residual: vs the 1e-13 oracle solution
-    Xo, _ = O.solve_block(dims, BC, U, m, r.beta, B, 1e-13)
+    # the action is quadratic in the residual: vs the 1e-14 oracle solution
     assert np.allclose(S, O.action(B, Xo, r.a0, r.alpha), rtol=1e-9)
 
 
@@ -131,7 +150,8 @@ def test_errors_and_limits(torch):
     assert e.value.code == bms.BMS_EBREAKDOWN
     # too few iterations
     X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-10, max_iter=5, raise_on_error=False)
-    assert st["status"] == bms.BMS_ENOCONV and st["iterations"] == 5
+    assert st["status"] == bms.BMS_ENOCONV and st["multishift_iterations"] == 5
+    _check_stats(st)
     # bad arguments
     for kw in [dict(shifts=[-1.0]), dict(shifts=[0.1] * 65)]:
         with pytest.raises(bms.BmsError) as e:
