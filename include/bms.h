@@ -188,6 +188,21 @@ int bms_solve(bms_ctx* ctx, double mass, int n, int n_shifts, const double* shif
 int bms_action(bms_ctx* ctx, int n, int n_shifts, double a0, const double* alpha, const void* B,
                const void* X, double* S);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bms_action without
+ * any allocation. Same arguments, result and errors as bms_action. Its
+ * scratch (residues, partial sums, the n sums; at most 0.55 MB for n = 32) is
+ * a static 1 MiB device array per GPU, held until the process ends; the
+ * call runs on the context's stream (the one given to bms_create), creates
+ * no stream or event and blocks until S is written. Calls that overlap on one
+ * GPU (other streams or host threads) share that array and race. A shape
+ * whose scratch would exceed 1 MiB is rejected with BMS_EINVAL (none exists
+ * within BMS_MAX_RHS).
+ */
+int bms_action_noalloc(bms_ctx* ctx, int n, int n_shifts, double a0, const double* alpha,
+                       const void* B, const void* X, double* S);
+
 #define BMS_FORCE_RAW 0 /* G = dS/dRe U + i dS/dIm U, [mu][idx][3][3] complex128 */
 #define BMS_FORCE_LIE 1 /* F^a = -dS/d omega^a for U -> exp(i omega^a T^a) U, T^a = lambda_a/2,
                            [mu][idx][8] float64 */

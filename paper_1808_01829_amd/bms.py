@@ -43,7 +43,7 @@ KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small", "force"]
 EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create", "bms_destroy",
            "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",
            "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant",
-           "bms_get_variant", "bms_autotune", "bms_solve_batch"]
+           "bms_get_variant", "bms_autotune", "bms_solve_batch", "bms_action_noalloc"]
 
 
 class bms_opts(ctypes.Structure):
@@ -104,6 +104,7 @@ def _lib():
         L.bms_solve.argtypes = [vp, d, i, i, dp, d, i, ctypes.POINTER(bms_opts), vp, vp,
                                 ctypes.POINTER(bms_stats)]
         L.bms_action.argtypes = [vp, i, i, d, dp, vp, vp, dp]
+        L.bms_action_noalloc.argtypes = [vp, i, i, d, dp, vp, vp, dp]
         L.bms_force.argtypes = [vp, i, i, dp, vp, vp, i]
         L.bms_timing_enable.argtypes = [vp, i]
         L.bms_set_variant.argtypes = [vp, i, i]
@@ -215,6 +216,14 @@ def bms_action(ctx, n, a0, alpha, B, X):
     ns = len(alpha)
     _check(ctx, _lib().bms_action(ctx, int(n), ns, float(a0), _doubles(alpha), _ptr(B), _ptr(X),
                                   S))
+    return [S[i] for i in range(n)]
+
+
+def bms_action_noalloc(ctx, n, a0, alpha, B, X):
+    S = (ctypes.c_double * n)()
+    ns = len(alpha)
+    _check(ctx, _lib().bms_action_noalloc(ctx, int(n), ns, float(a0), _doubles(alpha), _ptr(B),
+                                          _ptr(X), S))
     return [S[i] for i in range(n)]
 
 
