@@ -179,9 +179,12 @@ def action_measure(ctx, r, Bd, X, torch, reps=5):
 
 
 def force_measure(bms, torch, np, configs, reps=3):
-    """The force kernel at the force workload (K = n_pf x N_s columns), random
-    solutions (its cost does not depend on their values): time, algorithmic
-    GB/s and FP64 TFLOP/s against both roofs."""
+    """The whole bms_force call at the force workload (K = n_pf x N_s
+    columns), random solutions (its cost does not depend on their values):
+    time, algorithmic GB/s (every solution, the FP64 links and the output
+    once) and FP64 TFLOP/s (y = D_oe x and the outer products: 1152 flops per
+    odd site and column) against both roofs; the hops + per-link path
+    (variant 0) timed beside it."""
     from paper_1808_01829_amd.inputs import random_gauge
     wf = configs.WORKLOADS["c4"]
     rf = configs.workload_coefficients("c4")
@@ -192,24 +195,33 @@ def force_measure(bms, torch, np, configs, reps=3):
     g = torch.Generator(device="cuda").manual_seed(7002)
     X = torch.randn((ns, vh, 3, n), dtype=torch.complex128, device="cuda", generator=g)
     alpha = list(rf.alpha)
-    ctx.force(alpha, X)  # warm-up (scratch allocation, Y buffer)
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    for _ in range(reps):
-        ctx.force(alpha, X)
-    torch.cuda.synchronize()
-    ms, nl, by = ctx.timing_read()["force"]
-    ctx.timing(False)
-    us = 1e3 * ms / nl
     vol = int(np.prod(dims))
-    flops = 4.0 * vol * n * ns * 78  # per link and column: 3 scalings, 9 conj. FMAs
-    gbs = by / nl / (us * 1e-6) / 1e9
+    flops = (vol // 2) * n * ns * 1152.0
+    res = {}
+    for v in (-1, 0):
+        ctx.set_variant(bms.BMS_KERNEL_FORCE, v)
+        ctx.force(alpha, X)  # warm-up (scratch allocation)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        for _ in range(reps):
+            ctx.force(alpha, X)
+        torch.cuda.synchronize()
+        ms, nl, by = ctx.timing_read()["force"]
+        ctx.timing(False)
+        us = 1e3 * ms / nl
+        res[v] = (us, by / nl)
+    ctx.set_variant(bms.BMS_KERNEL_FORCE, -1)
+    us, nbytes = res[-1]
+    gbs = nbytes / (us * 1e-6) / 1e9
     tf = flops / (us * 1e-6) / 1e12
-    return dict(kernel="k_force", workload="c4: %s, n_pf=%d, %d shifts (K=%d), FP64" % (
-        "x".join(map(str, dims)), n, ns, n * ns), avg_us=round(us, 1),
-        algorithmic_bytes=round(by / nl), flops=flops, gbs=round(gbs, 1),
-        hbm_frac=round(gbs / HBM_PEAK_GBS, 4), tflops=round(tf, 2),
-        fp64_valu_frac=round(tf / FP64_VALU_PEAK_TFLOPS, 4))
+    return dict(kernel="k_force_fused (whole bms_force call)",
+                workload="c4: %s, n_pf=%d, %d shifts (K=%d), FP64" % (
+                    "x".join(map(str, dims)), n, ns, n * ns), avg_us=round(us, 1),
+                algorithmic_bytes=round(nbytes), flops=flops, gbs=round(gbs, 1),
+                hbm_frac=round(gbs / HBM_PEAK_GBS, 4), tflops=round(tf, 2),
+                fp64_valu_frac=round(tf / FP64_VALU_PEAK_TFLOPS, 4),
+                bound="fp64 valu", frac_of_binding_roof=round(tf / FP64_VALU_PEAK_TFLOPS, 4),
+                hops_then_per_link_us=round(res[0][0], 1))
 
 
 def main():

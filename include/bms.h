@@ -180,6 +180,23 @@ int bms_solve(bms_ctx* ctx, double mass, int n, int n_shifts, const double* shif
               int max_iter, const bms_opts* opts, const void* B, void* X, bms_stats* stats);
 
 /*
+ * Rational function of the operator applied to a block (eq. RA):
+ *   out = r(A) B = a0 B + sum_j alpha[j] (A + shifts[j])^-1 B,
+ * e.g. the pseudofermion heatbath phi = r(A) eta with r(x) ~ x^(+p/2) and
+ * Gaussian eta (Sec. II), or the accept-step action's solves with
+ * r(x) ~ x^(-p) fitted to relative error 1e-15 (the paper runs these at
+ * residual 1e-14, Sec. IV). The solutions X^(j) are those of bms_solve (same
+ * arguments, same stopping rule and errors, written to the caller's X
+ * [shift][cb][color][rhs]); out (device, [cb][color][rhs] complex128, must not
+ * alias B or X) is written only on BMS_OK. alpha[] (host) may have any sign
+ * (a fit of a positive power has negative residues).
+ */
+int bms_rational_apply(bms_ctx* ctx, double mass, int n, int n_shifts, double a0,
+                       const double* alpha, const double* shifts, double tol, int max_iter,
+                       const bms_opts* opts, const void* B, void* X, void* out,
+                       bms_stats* stats);
+
+/*
  * Pseudofermion action per column (Sec. II with eq. RA):
  *   S_i = Re phi_i^dag (a0 phi_i + sum_j alpha[j] X^(j) phi-column i),
  * from B (device, complex128 [cb][color][rhs]) and solutions X (device,
@@ -235,9 +252,9 @@ int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void
  *                       iteration P^(s) read and written, and in the other
  *                       two directions, X^(s) read, X^(s) and P^(s) written)
  *   BMS_KERNEL_SMALL    the n x n kernels (no block data)
- *   BMS_KERNEL_FORCE    the force kernel of bms_force (the D_oe hops before it
- *                       are not included): the solutions X and Y = D_oe X of
- *                       every shift read once, the FP64 links, the output
+ *   BMS_KERNEL_FORCE    the whole bms_force call (for variant 0 its D_oe hops
+ *                       included): every solution read once, the 4V FP64
+ *                       links once, the output written once
  * bms_timing_enable(ctx, 1) also clears the
  * accumulators; bms_timing_read returns them (host pointers, any may be NULL).
  */
@@ -273,7 +290,11 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  * and 1 in a tiled traversal (8 x 8 x 4 tiles in y, z, t of whole x-rows,
  * each (y, z) pencil on one XCD; lattices the tiles do not fit run in the
  * natural order), -1 = the default (1 where it applies, tiled in FP64 at
- * n >= 16). Other kernels are rejected with BMS_EINVAL;
+ * n >= 16). For BMS_KERNEL_FORCE: 1 and 2 = the fused kernel (y = D_oe x
+ * formed on chip for all n * n_shifts columns, each link loaded once and
+ * written once; links in registers, or in LDS with the loads two columns
+ * ahead), 0 = D_oe hops per shift into a buffer, then one lane group per
+ * link; -1 = the default (2). Other kernels are rejected with BMS_EINVAL;
  * other widths and precisions ignore the setting. Results do not depend on the variant beyond rounding
  * order.
  */

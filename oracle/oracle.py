@@ -10,6 +10,8 @@ multi-shift CG, force) and adds numpy routines:
   * sbcgrq          Algorithm 1 (SBCGrQ) in numpy, in the paper's order and
                     notation, using the C operator; used for iteration counts
                     and for the recurrences' invariants.
+  * rational_apply  r(A) B = a0 B + sum_j a_j (A + b_j)^-1 B by plain CG per
+                    shift and column (heatbath and accept-step solves).
   * action          S = sum_i phi_i^dag (a0 phi_i + sum_j a_j X_ij), eq. RA.
   * force           dS/dU from the C oracle (derivation in staggered.c).
   * dense_operator  the explicit matrix of A + sigma on a small lattice.
@@ -249,6 +251,22 @@ def sbcgrq_lattice(dims, bc, U, mass, shifts, B, tol, maxiter=10000, freeze_tol=
 
 
 # ---- action and force ------------------------------------------------------
+
+def rational_apply(dims, bc, U, mass, a0, alpha, beta, B, tol=1e-14, maxiter=100000):
+    """r(A) B = a0 B + sum_j alpha_j (A + beta_j)^-1 B (eq. RA applied to a
+    block), every (A + beta_j)^-1 b_i by its own plain CG (no multi-shift
+    recurrence). Used for the pseudofermion heatbath phi = r_hb(A) eta and
+    the accept-step solves (Sec. II, Sec. IV). Returns (out, X[shift])."""
+    B = _c(B)
+    X = np.empty((len(beta),) + B.shape, dtype=np.complex128)
+    for s, sig in enumerate(beta):
+        for j in range(B.shape[2]):
+            x, _, _ = cg(dims, bc, U, mass, float(sig), np.ascontiguousarray(B[..., j]), tol,
+                         maxiter)
+            X[s, ..., j] = x
+    out = a0 * B + np.tensordot(np.asarray(alpha, dtype=np.float64), X, axes=(0, 0))
+    return out, X
+
 
 def action(B, X, a0, alpha):
     """Per-column S_i = Re phi_i^dag (a0 phi_i + sum_j a_j X_ij) (eq. RA applied

@@ -43,7 +43,8 @@ KERNEL_NAMES = ["hop", "gram", "cholqr_gram", "update", "small", "force"]
 EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create", "bms_destroy",
            "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",
            "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant",
-           "bms_get_variant", "bms_autotune", "bms_solve_batch", "bms_action_noalloc"]
+           "bms_get_variant", "bms_autotune", "bms_solve_batch", "bms_action_noalloc",
+           "bms_rational_apply"]
 
 
 class bms_opts(ctypes.Structure):
@@ -104,6 +105,8 @@ def _lib():
         L.bms_solve.argtypes = [vp, d, i, i, dp, d, i, ctypes.POINTER(bms_opts), vp, vp,
                                 ctypes.POINTER(bms_stats)]
         L.bms_action.argtypes = [vp, i, i, d, dp, vp, vp, dp]
+        L.bms_rational_apply.argtypes = [vp, d, i, i, d, dp, dp, d, i, ctypes.POINTER(bms_opts),
+                                         vp, vp, vp, ctypes.POINTER(bms_stats)]
         L.bms_action_noalloc.argtypes = [vp, i, i, d, dp, vp, vp, dp]
         L.bms_force.argtypes = [vp, i, i, dp, vp, vp, i]
         L.bms_timing_enable.argtypes = [vp, i]
@@ -206,6 +209,26 @@ def bms_solve(ctx, mass, n, shifts, tol, max_iter, opts, B, X, want_residuals=Tr
     stats["status"] = rc
     if res is not None:
         stats["true_residual"] = [[res[s * n + i] for i in range(n)] for s in range(ns)]
+    if raise_on_error:
+        _check(ctx, rc)
+    return rc, stats
+
+
+def bms_rational_apply(ctx, mass, n, a0, alpha, shifts, tol, max_iter, opts, B, X, out,
+                       raise_on_error=True):
+    """out = a0 B + sum_j alpha_j (A + shifts_j)^-1 B; X receives the solutions.
+    Returns (status, stats dict)."""
+    ns = len(shifts)
+    st = bms_stats()
+    res = (ctypes.c_double * (ns * n))()
+    st.true_residual = ctypes.cast(res, ctypes.POINTER(ctypes.c_double))
+    rc = _lib().bms_rational_apply(ctx, float(mass), int(n), ns, float(a0), _doubles(alpha),
+                                   _doubles(shifts), float(tol), int(max_iter),
+                                   ctypes.byref(opts) if opts is not None else None, _ptr(B),
+                                   _ptr(X), _ptr(out), ctypes.byref(st))
+    stats = _stats_dict(st)
+    stats["status"] = rc
+    stats["true_residual"] = [[res[s * n + i] for i in range(n)] for s in range(ns)]
     if raise_on_error:
         _check(ctx, rc)
     return rc, stats
@@ -355,6 +378,22 @@ class Context:
         rc, stats = bms_solve(self.h, mass, n, list(shifts), tol, max_iter, opts, B, X,
                               raise_on_error=raise_on_error)
         return X, stats
+
+    def rational_apply(self, mass, r, B, tol=1e-10, max_iter=10000, opts=None,
+                       raise_on_error=True, **kw):
+        """r(A) B for a rational approximation r (a0, alpha, beta); returns
+        (out, X, stats) with X the shifted solutions."""
+        import torch
+        n = self._block(B, torch.complex128)
+        if opts is None:
+            opts = bms_default_opts()
+        for k, v in kw.items():
+            setattr(opts, k, v)
+        X = torch.empty((len(r.beta),) + tuple(B.shape), dtype=torch.complex128, device=B.device)
+        out = torch.empty_like(B)
+        _, stats = bms_rational_apply(self.h, mass, n, r.a0, list(r.alpha), list(r.beta), tol,
+                                      max_iter, opts, B, X, out, raise_on_error=raise_on_error)
+        return out, X, stats
 
     def action(self, a0, alpha, B, X):
         n = B.shape[2]

@@ -247,6 +247,11 @@ extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
     c->gram_variant = variant;
     return BMS_OK;
   }
+  if (kernel == BMS_KERNEL_FORCE) {
+    if (variant < -1 || variant > 2) return set_err(c, BMS_EINVAL, "force variant must be in [-1, 2]");
+    c->force_variant = variant;
+    return BMS_OK;
+  }
   if (kernel != BMS_KERNEL_UPDATE) return set_err(c, BMS_EINVAL, "no variants for kernel %d", kernel);
   if (variant < -1 || variant > 6) return set_err(c, BMS_EINVAL, "variant must be in [-1, 6]");
   c->update_variant = variant;

@@ -57,6 +57,9 @@ hipError_t launch_resid_block(hipStream_t st, int rows, int n, const void* B, co
                               const double* cs, const double* cb, void* R, const int* skip);
 hipError_t launch_axpy_cols(hipStream_t st, int rows, int n, void* X, const void* E,
                             const double* cs);
+// out = a0 B + sum_s alpha[s] X[s] over blk complex elements (alpha host array)
+hipError_t launch_rational_combine(hipStream_t st, size_t blk, int ns, double a0,
+                                   const double* alpha, const void* B, const void* X, void* out);
 hipError_t launch_gather_col(hipStream_t st, int rows, int n, int col, const void* src, void* dst);
 hipError_t launch_scatter_axpy_col(hipStream_t st, int rows, int n, int col, void* X,
                                    const void* e, double scale);

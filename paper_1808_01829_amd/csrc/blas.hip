@@ -1390,6 +1390,33 @@ __global__ __launch_bounds__(BMS_WG) void k_axpy_cols(int rows, int n, double2* 
   X[i] = cadd(X[i], cscale(E[i], cs[i % n]));
 }
 
+// out = a0 B + sum_s alpha[s] X[s] (eq. RA applied to a block, from the
+// shifted solutions): one pass over B and every X[s], two complex elements
+// per thread, the terms added in shift order.
+struct CombineArgs {
+  size_t blk;  // complex elements per block
+  int ns;
+  double a0;
+  double alpha[BMS_MAX_SHIFTS];
+};
+
+__global__ __launch_bounds__(BMS_WG) void k_rational_combine(CombineArgs a,
+                                                             const double2* __restrict__ B,
+                                                             const double2* __restrict__ X,
+                                                             double2* __restrict__ out) {
+  const size_t i = 2 * ((size_t)blockIdx.x * BMS_WG + threadIdx.x);
+  if (i >= a.blk) return;
+  const bool two = i + 1 < a.blk;
+  double2 v0 = cscale(B[i], a.a0), v1 = two ? cscale(B[i + 1], a.a0) : make_double2(0, 0);
+  for (int s = 0; s < a.ns; ++s) {
+    const double2* xs = X + (size_t)s * a.blk;
+    v0 = cadd(v0, cscale(xs[i], a.alpha[s]));
+    if (two) v1 = cadd(v1, cscale(xs[i + 1], a.alpha[s]));
+  }
+  out[i] = v0;
+  if (two) out[i + 1] = v1;
+}
+
 // X64[xmap[s]] += X32[s]; X32[s] = 0 for every shift (FP32 increments into
 // the FP64 solutions)
 struct FlushArgs {
@@ -1452,6 +1479,18 @@ hipError_t launch_axpy_cols(hipStream_t st, int rows, int n, void* X, const void
                             const double* cs) {
   k_axpy_cols<<<grid_for((size_t)rows * n), BMS_WG, 0, st>>>(rows, n, (double2*)X,
                                                             (const double2*)E, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rational_combine(hipStream_t st, size_t blk, int ns, double a0,
+                                   const double* alpha, const void* B, const void* X, void* out) {
+  CombineArgs a;
+  a.blk = blk;
+  a.ns = ns;
+  a.a0 = a0;
+  for (int s = 0; s < BMS_MAX_SHIFTS; ++s) a.alpha[s] = s < ns ? alpha[s] : 0.0;
+  k_rational_combine<<<grid_for((blk + 1) / 2), BMS_WG, 0, st>>>(a, (const double2*)B,
+                                                                 (const double2*)X, (double2*)out);
   return hipGetLastError();
 }
 

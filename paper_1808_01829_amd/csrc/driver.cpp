@@ -15,6 +15,7 @@ int* variant_slot(bms_ctx* c, int kernel) {
     case BMS_KERNEL_HOP: return &c->hop_variant;
     case BMS_KERNEL_GRAM: return &c->gram_variant;
     case BMS_KERNEL_UPDATE: return &c->update_variant;
+    case BMS_KERNEL_FORCE: return &c->force_variant;
     default: return nullptr;
   }
 }

@@ -7,6 +7,8 @@
 // Every link joins an even and an odd site, so each is written exactly once.
 #include <string.h>
 
+#include <cmath>
+
 #include <vector>
 
 #include "internal.h"
@@ -140,6 +142,230 @@ __global__ __launch_bounds__(BMS_WG) void k_force(ForceArgs a, int lpl) {
   F[7] = 0.5 / sqrt(3.0) * (w[0].y + w[4].y - 2.0 * w[8].y);  // lambda_8
 }
 
+// Quad sum by DPP: every lane of each group of four ends with the group's sum.
+__device__ __forceinline__ double dpp_xor1(double v) {
+  long long u = __builtin_bit_cast(long long, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0xB1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double dpp_xor2(double v) {
+  long long u = __builtin_bit_cast(long long, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)u, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x4E, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 quad_sum(double2 v) {
+  v.x += dpp_xor1(v.x);
+  v.y += dpp_xor1(v.y);
+  v.x += dpp_xor2(v.x);
+  v.y += dpp_xor2(v.y);
+  return v;
+}
+
+// Fused force, one odd site z per 16 lanes. Every link joins an odd and an
+// even site, so the links of z's forward hops (z, mu) and of its backward
+// hops (z - mu, mu) cover each link of the lattice once. Lane q = lane % 4
+// of the site owns direction mu = q, both links (as the half hop D_oe stores
+// them: 1/2 eta b U_mu(z) and -1/2 eta b' U_mu(z-mu)^dag); lane
+// g = (lane / 4) % 4 takes the flat columns c = g, g + 4, ... of the
+// K = n * N_s columns (c = shift * n + column). Per column the four q-lanes
+// form their share of y(z) = (D_oe x)(z) from x(z + mu) and x(z - mu), add
+// the shares by DPP (a quad), and accumulate
+//   M_a += alpha x(z + mu) y(z)^dag     (link (z, mu),      z odd)
+//   M_b += alpha y(z) x(z - mu)^dag     (link (z - mu, mu), z - mu even),
+// so y never leaves the registers and each x load serves both. At the end the
+// four g-lanes add their partial 3 x 3 sums and write each link once.
+//
+// LDS_LINKS: the links wait in LDS (18 KB per work-group) instead of 72
+// registers, read back every column; the registers freed hold the x loads of
+// the next PF columns, issued before the current column is computed.
+constexpr int kForceSites = BMS_WG / 16;  // odd sites per work-group
+constexpr int kLinkPitch = 8 * 9 + 1;     // complex per site in LDS (one pad)
+
+struct FCol {
+  double2 va[3], vb[3];
+  double al;
+};
+
+template <int PF, bool LDS_LINKS, int WAVES>
+__global__ __launch_bounds__(BMS_WG, WAVES) void k_force_fused(ForceArgs a) {
+  const Geom& g = a.g;
+  const int lane = threadIdx.x & 63;
+  const int q = lane & 3, gl = (lane >> 2) & 3;
+  const int sl = threadIdx.x >> 4;  // site within the work-group
+  const uint32_t z0 = blockIdx.x * kForceSites + sl;
+  const bool live = z0 < (uint32_t)g.vh;
+  // dead sites of the last block compute on the last site and write nothing,
+  // so every lane of a quad and of a g-group takes part in the shuffles
+  const uint32_t z = live ? z0 : (uint32_t)g.vh - 1;
+  const int mu = q;
+  SiteCoord sc = site_coords(z, g, 1);
+  const int co[4] = {sc.x, sc.y, sc.z, sc.t};
+  const int ef = neighbour_cb((int)z, sc, g, mu, 1);
+  const int eb = neighbour_cb((int)z, sc, g, mu, -1);
+  int esum = 0;
+  for (int nu = 0; nu < mu; ++nu) esum += co[nu];
+  const double eta = (esum & 1) ? -1.0 : 1.0;
+  const double bf = co[mu] == g.L[mu] - 1 ? (double)a.bc[mu] : 1.0;
+  const double be = co[mu] == 0 ? (double)a.bc[mu] : 1.0;
+  const double2* L = a.links + a.pstride;  // parity 1 (odd output sites)
+  __shared__ double2 lds[LDS_LINKS ? kForceSites * kLinkPitch : 1];
+  double2 la[9], lb[9];
+  if (LDS_LINKS) {
+    // the four g-lanes of (site, q) stage the site's links mu and 4 + mu
+    for (int e = gl; e < 9; e += 4) {
+      lds[sl * kLinkPitch + mu * 9 + e] = L[link_off(z, mu, e, a.sbl)];
+      lds[sl * kLinkPitch + (4 + mu) * 9 + e] = L[link_off(z, 4 + mu, e, a.sbl)];
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      la[e] = L[link_off(z, mu, e, a.sbl)];
+      lb[e] = L[link_off(z, 4 + mu, e, a.sbl)];
+    }
+  }
+  double2 ma[9], mb[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    ma[e] = make_double2(0, 0);
+    mb[e] = make_double2(0, 0);
+  }
+  const int n = a.n;
+  const int K = n * a.ns;
+  const size_t blk = (size_t)g.vh * 3 * n;
+  const double2* xf = a.X + (size_t)ef * 3 * n;
+  const double2* xbk = a.X + (size_t)eb * 3 * n;
+  // load cursor: flat column c = j * n + i = 4 t + g. Every lane runs the
+  // same steps; columns past K load column 0 and add nothing.
+  const int T = (K + 3) >> 2;
+  int j = gl / n, i = gl - (gl / n) * n, c = gl;
+  auto load = [&](FCol& f) {
+    const bool valid = c < K;
+    const size_t o = valid ? (size_t)j * blk + i : 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      f.va[b] = xf[o + (size_t)b * n];
+      f.vb[b] = xbk[o + (size_t)b * n];
+    }
+    f.al = valid ? a.alpha[valid ? j : 0] : 0.0;
+    c += 4;
+    i += 4;
+    while (i >= n) {
+      i -= n;
+      ++j;
+    }
+  };
+  int lofs = sl * kLinkPitch + mu * 9;
+  auto compute = [&](const FCol& f) {
+    if (LDS_LINKS) {
+      // a fresh address every column keeps the LDS reads inside the loop
+      asm volatile("" : "+v"(lofs));
+    }
+    double2 y[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double2 t = make_double2(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double2 lfa = LDS_LINKS ? lds[lofs + 3 * r + b] : la[3 * r + b];
+        const double2 lfb = LDS_LINKS ? lds[lofs + 36 + 3 * r + b] : lb[3 * r + b];
+        t = cfma(lfa, f.va[b], t);
+        t = cfma(lfb, f.vb[b], t);
+      }
+      y[r] = cscale(quad_sum(t), f.al);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        ma[3 * r + b] = cjfma(y[b], f.va[r], ma[3 * r + b]);  // x_f[r] conj(y[b])
+        mb[3 * r + b] = cjfma(f.vb[b], y[r], mb[3 * r + b]);  // y[r] conj(x_b[b])
+      }
+  };
+  FCol buf[PF];
+#pragma unroll
+  for (int u = 0; u < PF; ++u) load(buf[u]);
+  for (int t = 0; t < T; t += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const FCol cur = buf[u];
+      load(buf[u]);  // PF columns ahead
+      compute(cur);
+    }
+  }
+  // add the four column groups (lanes 4 and 8 apart)
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    ma[e].x += __shfl_xor(ma[e].x, 4);
+    ma[e].y += __shfl_xor(ma[e].y, 4);
+    mb[e].x += __shfl_xor(mb[e].x, 4);
+    mb[e].y += __shfl_xor(mb[e].y, 4);
+    ma[e].x += __shfl_xor(ma[e].x, 8);
+    ma[e].y += __shfl_xor(ma[e].y, 8);
+    mb[e].x += __shfl_xor(mb[e].x, 8);
+    mb[e].y += __shfl_xor(mb[e].y, 8);
+  }
+  if (!live) return;
+  // M_mu(z) = -eta b_f sum alpha x(z+mu) y(z)^dag ; M_mu(z-mu) = +eta b_e sum alpha y(z) x(z-mu)^dag
+  const double sa = -eta * bf, sb = eta * be;
+  const uint32_t vol = 2u * (uint32_t)g.vh;
+  const uint32_t idx_a = (uint32_t)(sc.x + g.L[0] * (sc.y + g.L[1] * (sc.z + g.L[2] * sc.t)));
+  int cb_[4] = {sc.x, sc.y, sc.z, sc.t};
+  cb_[mu] = co[mu] == 0 ? g.L[mu] - 1 : co[mu] - 1;
+  const uint32_t idx_b = (uint32_t)(cb_[0] + g.L[0] * (cb_[1] + g.L[1] * (cb_[2] + g.L[2] * cb_[3])));
+  const bool second = gl >= 2;  // lanes g = 0, 1 write link a; g = 2, 3 link b
+  const uint32_t idx = second ? idx_b : idx_a;
+  const double sg = second ? sb : sa;
+  double2 m[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) m[e] = cscale(second ? mb[e] : ma[e], sg);
+  const size_t lo = (size_t)mu * vol + idx;
+  if (!a.lie) {
+    // G = M^dag, the two lanes of a link split its nine entries
+    double2* G = a.G + lo * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+      if ((e & 1) == (gl & 1)) G[e] = cconj(m[3 * (e % 3) + e / 3]);
+    return;
+  }
+  if (gl & 1) return;
+  // the link itself: U = 2 eta b_f L_a, or U = (-2 eta b_e L_b)^dag
+  double2 u[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (LDS_LINKS)
+        u[3 * r + b] = second ? cconj(cscale(lds[sl * kLinkPitch + (4 + mu) * 9 + 3 * b + r],
+                                             -2.0 * eta * be))
+                              : cscale(lds[sl * kLinkPitch + mu * 9 + 3 * r + b], 2.0 * eta * bf);
+      else
+        u[3 * r + b] = second ? cconj(cscale(lb[3 * b + r], -2.0 * eta * be))
+                              : cscale(la[3 * r + b], 2.0 * eta * bf);
+    }
+  double2 w[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double2 t = make_double2(0, 0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t = cfma(u[3 * r + k], m[3 * k + b], t);
+      w[3 * r + b] = t;
+    }
+  double* F = a.F + lo * 8;
+  F[0] = 0.5 * (w[3].y + w[1].y);
+  F[1] = 0.5 * (-(w[3].x) + w[1].x);
+  F[2] = 0.5 * (w[0].y - w[4].y);
+  F[3] = 0.5 * (w[6].y + w[2].y);
+  F[4] = 0.5 * (-(w[6].x) + w[2].x);
+  F[5] = 0.5 * (w[7].y + w[5].y);
+  F[6] = 0.5 * (-(w[7].x) + w[5].x);
+  F[7] = 0.5 / sqrt(3.0) * (w[0].y + w[4].y - 2.0 * w[8].y);
+}
+
 }  // namespace
 
 extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const void* X, void* out,
@@ -149,15 +375,15 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   if (ns < 1 || ns > BMS_MAX_SHIFTS) return set_err(c, BMS_EINVAL, "bad n_shifts");
   if (!alpha || !X || !out) return set_err(c, BMS_EINVAL, "null pointer");
   if (flags != BMS_FORCE_RAW && flags != BMS_FORCE_LIE) return set_err(c, BMS_EINVAL, "bad flags");
+  for (int s = 0; s < ns; ++s)
+    if (!std::isfinite(alpha[s])) return set_err(c, BMS_EINVAL, "alpha[%d] not finite", s);
   if (!c->gauge_set) return set_err(c, BMS_ESTATE, "no gauge field set");
   int rc;
   if ((rc = stream_begin(c))) return rc;
-  size_t blk = (size_t)c->vh * 3 * n;
-  void* Y;
-  if ((rc = scratch_buf(c, S_Y, blk * ns * sizeof(double2), &Y))) return rc;
-  for (int s = 0; s < ns; ++s)
-    HIP_TRY(c, launch_hop<double>(c, 1, n, (const double2*)X + s * blk, (double2*)Y + s * blk,
-                                  nullptr, 0.0, 1.0, nullptr));
+  const size_t blk = (size_t)c->vh * 3 * n;
+  const bool fused = c->force_variant != 0;
+  void* Y = nullptr;
+  if (!fused && (rc = scratch_buf(c, S_Y, blk * ns * sizeof(double2), &Y))) return rc;
   ForceArgs a;
   memset(&a, 0, sizeof a);
   a.g = c->geom;
@@ -173,20 +399,38 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   a.G = (double2*)out;
   a.F = (double*)out;
   for (int s = 0; s < ns; ++s) a.alpha[s] = alpha[s];
-  // lanes per link: the block width rounded up to a power of two, at most 16
-  int lpl = 1;
-  while (lpl < n && lpl < 16) lpl <<= 1;
-  uint32_t nthr = 4u * (uint32_t)c->vol * (uint32_t)lpl;
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (c->timing) {
+    // the whole call is timed (for variant 0 its D_oe hops included)
     HIP_TRY(c, hipEventCreate(&ev[0]));
     HIP_TRY(c, hipEventCreate(&ev[1]));
     HIP_TRY(c, hipEventRecord(ev[0], c->stream));
   }
-  k_force<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(a, lpl);
+  if (fused) {
+    // 16 lanes per odd site. Variants: 1 links in registers, loads one
+    // column ahead; 2 (default) links in LDS, loads two columns ahead.
+    // Measured at 16^3 x 32, K = 128: 511 and 499 us (hops + per-link
+    // kernel, variant 0: 998 us)
+    const dim3 grid((c->vh + kForceSites - 1) / kForceSites);
+    const int fv = c->force_variant < 0 ? 2 : c->force_variant;
+    if (fv == 1)
+      k_force_fused<1, false, 2><<<grid, BMS_WG, 0, c->stream>>>(a);
+    else
+      k_force_fused<2, true, 2><<<grid, BMS_WG, 0, c->stream>>>(a);
+  } else {
+    // Y = D_oe X per shift, then a lane group per link (the block width
+    // rounded up to a power of two, at most 16)
+    for (int s = 0; s < ns; ++s)
+      HIP_TRY(c, launch_hop<double>(c, 1, n, (const double2*)X + s * blk, (double2*)Y + s * blk,
+                                    nullptr, 0.0, 1.0, nullptr));
+    int lpl = 1;
+    while (lpl < n && lpl < 16) lpl <<= 1;
+    const uint32_t nthr = 4u * (uint32_t)c->vol * (uint32_t)lpl;
+    k_force<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(a, lpl);
+  }
   HIP_TRY(c, hipGetLastError());
   if (c->timing) {
-    // algorithmic bytes: X and Y of every shift once, the 4V FP64 links, the output
+    // algorithmic bytes: every solution read once, the 4V FP64 links once, the output
     HIP_TRY(c, hipEventRecord(ev[1], c->stream));
     HIP_TRY(c, hipEventSynchronize(ev[1]));
     float ms = 0;
@@ -194,7 +438,7 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
     const double vol = (double)c->vol;
     c->kt_ms[BMS_KERNEL_FORCE] += ms;
     c->kt_launches[BMS_KERNEL_FORCE] += 1;
-    c->kt_bytes[BMS_KERNEL_FORCE] += 2.0 * ns * blk * sizeof(double2) + 4 * vol * 9 * 16 +
+    c->kt_bytes[BMS_KERNEL_FORCE] += (double)ns * blk * sizeof(double2) + 4 * vol * 9 * 16 +
                                      (a.lie ? 4 * vol * 8 * 8 : 4 * vol * 9 * 16);
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);

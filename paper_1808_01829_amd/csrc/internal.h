@@ -97,6 +97,7 @@ struct bms_ctx {
   int update_variant = -1;
   int gram_variant = -1;
   int hop_variant = -1;
+  int force_variant = -1;  // 0: D_oe hops per shift + per-link kernel; else fused
   // per-kernel timing (bms_timing_enable)
   bool timing = false;
   double kt_ms[BMS_NKERNELS] = {0};

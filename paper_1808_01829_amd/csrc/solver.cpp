@@ -932,6 +932,25 @@ extern "C" int bms_solve(bms_ctx* c, double mass, int n, int ns, const double* s
   return rc ? rc : rc2;
 }
 
+extern "C" int bms_rational_apply(bms_ctx* c, double mass, int n, int ns, double a0,
+                                  const double* alpha, const double* shifts, double tol,
+                                  int max_iter, const bms_opts* opts, const void* B, void* X,
+                                  void* out, bms_stats* st) {
+  if (!c) return BMS_EINVAL;
+  int rc = validate_solve(c, mass, n, ns, shifts, tol, max_iter, opts, B, X);
+  if (rc) return rc;
+  if (!alpha || !out) return set_err(c, BMS_EINVAL, "null alpha or out");
+  if (out == X) return set_err(c, BMS_EINVAL, "out and X must not alias");
+  if (!std::isfinite(a0)) return set_err(c, BMS_EINVAL, "a0 not finite");
+  for (int s = 0; s < ns; ++s)
+    if (!std::isfinite(alpha[s])) return set_err(c, BMS_EINVAL, "alpha[%d] not finite", s);
+  rc = bms_solve(c, mass, n, ns, shifts, tol, max_iter, opts, B, X, st);
+  if (rc != BMS_OK) return rc;
+  if ((rc = stream_begin(c))) return rc;
+  HIP_TRY(c, launch_rational_combine(c->stream, (size_t)3 * c->vh * n, ns, a0, alpha, B, X, out));
+  return stream_end(c);
+}
+
 extern "C" int bms_action(bms_ctx* c, int n, int ns, double a0, const double* alpha,
                           const void* B, const void* X, double* S) {
   if (!c) return BMS_EINVAL;

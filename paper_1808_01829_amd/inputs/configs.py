@@ -59,17 +59,62 @@ def workload_coefficients(name):
     return coefficients(w["power"], m2, 16.0 + m2, w["poles"])
 
 
-def write_cache():
-    """Fit every workload's coefficients and store them (run as a script)."""
-    tab = {}
+# Heatbath and accept-step fits (Sec. II: the pseudofermions are drawn as
+# phi = [M^dag M]^(+p/2) eta from Gaussian eta, so that the action
+# phi^dag [M^dag M]^(-p) phi equals eta^dag eta; Sec. IV runs these solves at
+# residual 1e-14 with rational approximations of relative error below 1e-15).
+# The pole counts reach that error on the workload's spectrum interval.
+HMC_FITS = {
+    "c2": dict(heatbath_poles=20, accept_poles=21),
+}
+
+
+def heatbath_coefficients(name):
+    """r_hb(x) ~ x^(+p/2) for the workload's action exponent p."""
+    w = WORKLOADS[name]
+    m2 = w["mass"] ** 2
+    return coefficients(-0.5 * w["power"], m2, 16.0 + m2, HMC_FITS[name]["heatbath_poles"])
+
+
+def accept_coefficients(name):
+    """r(x) ~ x^(-p) at the accept-step accuracy."""
+    w = WORKLOADS[name]
+    m2 = w["mass"] ** 2
+    return coefficients(w["power"], m2, 16.0 + m2, HMC_FITS[name]["accept_poles"])
+
+
+def _fits():
+    """(label, power, lo, hi, poles) of every stored fit."""
+    out = []
     for name, w in WORKLOADS.items():
         m2 = w["mass"] ** 2
-        r = rational.remez(w["power"], m2, 16.0 + m2, w["poles"])
-        tab[_key(w["power"], m2, 16.0 + m2, w["poles"])] = r.as_dict()
-        print(name, "poles", w["poles"], "relative error %.3e" % r.error, flush=True)
+        out.append((name, w["power"], m2, 16.0 + m2, w["poles"]))
+    for name, h in HMC_FITS.items():
+        w = WORKLOADS[name]
+        m2 = w["mass"] ** 2
+        out.append((name + " heatbath", -0.5 * w["power"], m2, 16.0 + m2, h["heatbath_poles"]))
+        out.append((name + " accept", w["power"], m2, 16.0 + m2, h["accept_poles"]))
+    return out
+
+
+def write_cache(only_missing=True):
+    """Fit the coefficients and store them (run as a script). Entries already
+    in the cache are kept unless only_missing is False."""
+    tab = {}
+    if only_missing and os.path.exists(_CACHE):
+        with open(_CACHE) as f:
+            tab = json.load(f)
+    for label, power, lo, hi, poles in _fits():
+        key = _key(power, lo, hi, poles)
+        if key in tab:
+            continue
+        r = rational.remez(power, lo, hi, poles)
+        tab[key] = r.as_dict()
+        print(label, "poles", poles, "relative error %.3e" % r.error, flush=True)
     with open(_CACHE, "w") as f:
         json.dump(tab, f, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    write_cache()
+    import sys
+    write_cache(only_missing="--all" not in sys.argv)

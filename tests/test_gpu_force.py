@@ -43,10 +43,16 @@ def test_force_parity(torch, dims, n, name):
     c = bms.Context(dims, BC)
     c.set_gauge(to_dev(torch, U))
     Xd = to_dev(torch, Xo)  # the oracle's solutions as the kernel's input
-    G = to_np(c.force(r.alpha, Xd, bms.BMS_FORCE_RAW))
-    F = to_np(c.force(r.alpha, Xd, bms.BMS_FORCE_LIE))
-    assert rel(G, Go) < 1e-12
-    assert rel(F, Fo) < 1e-12
+    # the fused kernel (default) and the hops + per-link kernel (variant 0)
+    for v in (-1, 0):
+        c.set_variant(bms.BMS_KERNEL_FORCE, v)
+        G = to_np(c.force(r.alpha, Xd, bms.BMS_FORCE_RAW))
+        F = to_np(c.force(r.alpha, Xd, bms.BMS_FORCE_LIE))
+        print("force n=%d %s variant %d: raw %.1e, Lie %.1e" % (
+            n, "x".join(map(str, dims)), v, rel(G, Go), rel(F, Fo)))
+        assert rel(G, Go) < 1e-12
+        assert rel(F, Fo) < 1e-12
+    c.set_variant(bms.BMS_KERNEL_FORCE, -1)
     # the full GPU path (solve + force) agrees to the solver's accuracy
     X, st = c.solve(m, r.beta, to_dev(torch, B), tol=1e-12)
     F2 = to_np(c.force(r.alpha, X, bms.BMS_FORCE_LIE))
