@@ -300,6 +300,33 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  */
 int bms_set_variant(bms_ctx* ctx, int kernel, int variant);
 
+/*
+ * Traversal of the half hop for one precision (BMS_PREC_F64 or BMS_PREC_F32
+ * blocks): cfg = {ty, tz, tt, cap, nt}.
+ *   ty, tz, tt  tiles of whole x-rows, ty x tz x tt sites in y, z, t; the
+ *               (y, z) pencils of tiles go to the 8 XCDs in turn and each XCD
+ *               walks its pencils tile after tile along t (lattices the tiles do
+ *               not divide run in the natural order); ty = 0: natural order
+ *   cap         at most cap resident work-groups per compute unit (0: no cap;
+ *               -1: the built-in choice by block width)
+ *   nt          1: link loads with the non-temporal hint
+ * cfg = NULL or cfg[0] = -1 restores the built-in choice. Applies to the
+ * quad and per-group hop kernels alike (bms_set_variant picks the kernel);
+ * results do not depend on it. bms_get_hop_config returns the setting.
+ * Errors: BMS_EINVAL for a bad precision, extent, cap or nt.
+ */
+int bms_set_hop_config(bms_ctx* ctx, int precision, const int cfg[5]);
+int bms_get_hop_config(const bms_ctx* ctx, int precision, int cfg[5]);
+
+/*
+ * Cache file of bms_autotune (a text file of JSON lines, one per tuned
+ * problem shape; NULL or "" = no cache). With a cache set, bms_autotune
+ * first looks for the key (device architecture, lattice, n, n_shifts,
+ * precision) and applies the stored choice without timing anything; on a
+ * miss it times the candidates and appends the result.
+ */
+int bms_set_tune_cache(bms_ctx* ctx, const char* path);
+
 /* The variant currently set for a kernel class (BMS_KERNEL_HOP, _GRAM, _UPDATE). */
 int bms_get_variant(const bms_ctx* ctx, int kernel, int* variant);
 

@@ -44,7 +44,8 @@ EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create
            "bms_set_gauge", "bms_apply_hop", "bms_apply_mdagm", "bms_solve", "bms_action",
            "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant",
            "bms_get_variant", "bms_autotune", "bms_solve_batch", "bms_action_noalloc",
-           "bms_rational_apply"]
+           "bms_rational_apply", "bms_set_hop_config", "bms_get_hop_config",
+           "bms_set_tune_cache"]
 
 
 class bms_opts(ctypes.Structure):
@@ -113,6 +114,9 @@ def _lib():
         L.bms_set_variant.argtypes = [vp, i, i]
         L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         L.bms_get_variant.argtypes = [vp, i, ip]
+        L.bms_set_hop_config.argtypes = [vp, i, ip]
+        L.bms_get_hop_config.argtypes = [vp, i, ip]
+        L.bms_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
         L.bms_autotune.argtypes = [vp, d, i, i, dp, i, i, vp, vp]
         L.bms_solve_batch.argtypes = [i, ctypes.POINTER(vp), dp, ip, ip,
                                       ctypes.POINTER(dp), dp, ip, ctypes.POINTER(bms_opts),
@@ -269,6 +273,22 @@ def bms_get_variant(ctx, kernel):
     return v.value
 
 
+def bms_set_hop_config(ctx, precision, cfg):
+    """cfg = (ty, tz, tt, cap, nt), or None for the built-in choice."""
+    arr = (ctypes.c_int * 5)(*(cfg if cfg is not None else (-1, 0, 0, 0, 0)))
+    _check(ctx, _lib().bms_set_hop_config(ctx, int(precision), arr))
+
+
+def bms_get_hop_config(ctx, precision):
+    arr = (ctypes.c_int * 5)()
+    _check(ctx, _lib().bms_get_hop_config(ctx, int(precision), arr))
+    return tuple(arr)
+
+
+def bms_set_tune_cache(ctx, path):
+    _check(ctx, _lib().bms_set_tune_cache(ctx, path.encode() if path else None))
+
+
 def bms_autotune(ctx, mass, n, shifts, precision, iters, B, X):
     _check(ctx, _lib().bms_autotune(ctx, float(mass), int(n), len(shifts), _doubles(shifts),
                                     int(precision), int(iters), _ptr(B), _ptr(X)))
@@ -412,8 +432,20 @@ class Context:
         n = self._block(B, torch.complex128)
         X = torch.empty((len(shifts),) + tuple(B.shape), dtype=torch.complex128, device=B.device)
         bms_autotune(self.h, mass, n, list(shifts), precision, iters, B, X)
-        return {KERNEL_NAMES[k]: self.get_variant(k)
-                for k in (BMS_KERNEL_HOP, BMS_KERNEL_GRAM, BMS_KERNEL_UPDATE)}
+        out = {KERNEL_NAMES[k]: self.get_variant(k)
+               for k in (BMS_KERNEL_HOP, BMS_KERNEL_GRAM, BMS_KERNEL_UPDATE)}
+        out["hop_f64"] = bms_get_hop_config(self.h, BMS_PREC_F64)
+        out["hop_f32"] = bms_get_hop_config(self.h, BMS_PREC_F32)
+        return out
+
+    def set_hop_config(self, precision, cfg):
+        bms_set_hop_config(self.h, precision, cfg)
+
+    def get_hop_config(self, precision):
+        return bms_get_hop_config(self.h, precision)
+
+    def set_tune_cache(self, path):
+        bms_set_tune_cache(self.h, path)
 
     def timing(self, enable=True):
         bms_timing_enable(self.h, enable)

@@ -89,6 +89,8 @@ int ensure_device(bms_ctx* c) {
   HIP_TRY(c, hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   HIP_TRY(c, hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
                                    c->device));
+  HIP_TRY(c, hipDeviceGetAttribute(&c->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                   c->device));
   HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   HIP_TRY(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -255,5 +257,44 @@ extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
   if (kernel != BMS_KERNEL_UPDATE) return set_err(c, BMS_EINVAL, "no variants for kernel %d", kernel);
   if (variant < -1 || variant > 6) return set_err(c, BMS_EINVAL, "variant must be in [-1, 6]");
   c->update_variant = variant;
+  return BMS_OK;
+}
+
+extern "C" int bms_set_hop_config(bms_ctx* c, int precision, const int cfg[5]) {
+  if (!c) return BMS_EINVAL;
+  if (precision != BMS_PREC_F64 && precision != BMS_PREC_F32)
+    return set_err(c, BMS_EINVAL, "precision must be BMS_PREC_F64 or BMS_PREC_F32");
+  HopCfg h;
+  if (cfg && cfg[0] >= 0) {
+    const int ty = cfg[0], tz = cfg[1], tt = cfg[2], cap = cfg[3], nt = cfg[4];
+    if (ty > 0 && (tz < 1 || tt < 1 || ty > 4096 || tz > 4096 || tt > 4096))
+      return set_err(c, BMS_EINVAL, "tile extents must be >= 1");
+    if (cap < -1 || cap > 64) return set_err(c, BMS_EINVAL, "cap must be in [-1, 64]");
+    if (nt != 0 && nt != 1) return set_err(c, BMS_EINVAL, "nt must be 0 or 1");
+    h.ty = ty;
+    h.tz = ty > 0 ? tz : 8;
+    h.tt = ty > 0 ? tt : 4;
+    h.cap = cap;
+    h.nt = nt;
+  }
+  c->hop_cfg[precision == BMS_PREC_F64 ? 0 : 1] = h;
+  return BMS_OK;
+}
+
+extern "C" int bms_get_hop_config(const bms_ctx* c, int precision, int cfg[5]) {
+  if (!c || !cfg) return BMS_EINVAL;
+  if (precision != BMS_PREC_F64 && precision != BMS_PREC_F32) return BMS_EINVAL;
+  const HopCfg& h = c->hop_cfg[precision == BMS_PREC_F64 ? 0 : 1];
+  cfg[0] = h.ty;
+  cfg[1] = h.tz;
+  cfg[2] = h.tt;
+  cfg[3] = h.cap;
+  cfg[4] = h.nt;
+  return BMS_OK;
+}
+
+extern "C" int bms_set_tune_cache(bms_ctx* c, const char* path) {
+  if (!c) return BMS_EINVAL;
+  c->tune_cache = path ? path : "";
   return BMS_OK;
 }

@@ -1,7 +1,10 @@
 // Drivers above bms_solve: kernel-variant autotuning on the caller's problem
 // and a batch of independent solves (one context and stream each) run
 // concurrently on one GPU.
+#include <stdio.h>
 #include <string.h>
+
+#include <string>
 
 #include <thread>
 #include <vector>
@@ -46,6 +49,152 @@ extern "C" int bms_get_variant(const bms_ctx* c, int kernel, int* variant) {
   return BMS_OK;
 }
 
+namespace {
+
+// Events around `reps` pairs of half hops (D_oe then D_eo with the aux
+// epilogue) on the workspace blocks, in the current hop variant and
+// configuration: microseconds per pair.
+template <typename T>
+int time_hop_pair(bms_ctx* c, int n, void* e_in, void* o_mid, void* e_out, int reps, double* us) {
+  hipEvent_t ev[2];
+  HIP_TRY(c, hipEventCreate(&ev[0]));
+  HIP_TRY(c, hipEventCreate(&ev[1]));
+  HIP_TRY(c, launch_hop<T>(c, 1, n, e_in, o_mid, nullptr, 0.0, 1.0, nullptr));  // warm-up
+  HIP_TRY(c, launch_hop<T>(c, 0, n, o_mid, e_out, e_in, 0.5, -1.0, nullptr));
+  HIP_TRY(c, hipEventRecord(ev[0], c->stream));
+  for (int r = 0; r < reps; ++r) {
+    HIP_TRY(c, launch_hop<T>(c, 1, n, e_in, o_mid, nullptr, 0.0, 1.0, nullptr));
+    HIP_TRY(c, launch_hop<T>(c, 0, n, o_mid, e_out, e_in, 0.5, -1.0, nullptr));
+  }
+  HIP_TRY(c, hipEventRecord(ev[1], c->stream));
+  HIP_TRY(c, hipEventSynchronize(ev[1]));
+  float ms = 0;
+  HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  *us = 1e3 * ms / reps;
+  return BMS_OK;
+}
+
+// Search of the hop's traversal for one precision: natural order and several
+// tile shapes, each with 0..4 resident work-groups per compute unit and with
+// and without non-temporal link loads, plus the per-group kernel. Keeps the
+// fastest (variant and configuration); returns its time per hop pair.
+int tune_hop(bms_ctx* c, int n, bool fp64, double* best_us) {
+  const size_t blk = (size_t)3 * c->vh * n;
+  void *e_in, *o_mid, *e_out;
+  int rc;
+  if ((rc = scratch_buf(c, S_R2, blk * sizeof(double2), &e_in))) return rc;
+  if ((rc = scratch_buf(c, S_R1, blk * sizeof(double2), &o_mid))) return rc;
+  if ((rc = scratch_buf(c, S_R0, blk * sizeof(double2), &e_out))) return rc;
+  const int tiles[][3] = {{0, 0, 0},  {8, 8, 4},  {8, 8, 8}, {16, 8, 4}, {8, 16, 4},
+                          {4, 8, 8},  {16, 16, 2}, {4, 4, 8}, {8, 4, 8},  {16, 8, 2}};
+  const int slot = fp64 ? 0 : 1;
+  const HopCfg keep = c->hop_cfg[slot];
+  const int keep_v = c->hop_variant;
+  HopCfg best = keep;
+  int best_v = keep_v;
+  double bus = 1e300;
+  const int reps = 3;
+  for (int v : {-1, 0}) {
+    c->hop_variant = v;
+    for (const auto& t : tiles) {
+      if (t[0] > 0 && !hop_tiling_valid(c, n, t[0], t[1], t[2])) continue;
+      for (int cap = 0; cap <= 4; ++cap)
+        for (int nt = 0; nt <= 1; ++nt) {
+          if (cap > 0 && hop_cap_lds(c, cap) == 0) continue;  // cap not applicable here
+          HopCfg h;
+          h.ty = t[0];
+          h.tz = t[0] > 0 ? t[1] : 8;
+          h.tt = t[0] > 0 ? t[2] : 4;
+          h.cap = cap;
+          h.nt = nt;
+          c->hop_cfg[slot] = h;
+          double us = 0;
+          rc = fp64 ? time_hop_pair<double>(c, n, e_in, o_mid, e_out, reps, &us)
+                    : time_hop_pair<float>(c, n, e_in, o_mid, e_out, reps, &us);
+          if (rc) {
+            c->hop_cfg[slot] = keep;
+            c->hop_variant = keep_v;
+            return rc;
+          }
+          if (us < bus) {
+            bus = us;
+            best = h;
+            best_v = v;
+          }
+        }
+    }
+  }
+  c->hop_cfg[slot] = best;
+  c->hop_variant = best_v;
+  *best_us = bus;
+  return BMS_OK;
+}
+
+std::string tune_key(bms_ctx* c, int n, int ns, int precision) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|%d,%d,%d,%d|%d|%d|%d", arch.c_str(), c->dims[0], c->dims[1],
+           c->dims[2], c->dims[3], n, ns, precision);
+  return buf;
+}
+
+// The last cache line with this key, applied to the context; false if none.
+bool cache_lookup(bms_ctx* c, const std::string& key) {
+  FILE* f = fopen(c->tune_cache.c_str(), "r");
+  if (!f) return false;
+  char line[1024];
+  const std::string want = "{\"key\": \"" + key + "\",";
+  bool found = false;
+  int hv = -1, gv = -1, uv = -1, h64[5], h32[5];
+  while (fgets(line, sizeof line, f)) {
+    if (strncmp(line, want.c_str(), want.size()) != 0) continue;
+    int a, b, d, e[5], g[5];
+    if (sscanf(line + want.size(),
+               " \"hop\": %d, \"gram\": %d, \"update\": %d, \"hop_f64\": [%d, %d, %d, %d, %d], "
+               "\"hop_f32\": [%d, %d, %d, %d, %d]",
+               &a, &b, &d, &e[0], &e[1], &e[2], &e[3], &e[4], &g[0], &g[1], &g[2], &g[3],
+               &g[4]) == 13) {
+      found = true;
+      hv = a;
+      gv = b;
+      uv = d;
+      memcpy(h64, e, sizeof h64);
+      memcpy(h32, g, sizeof h32);
+    }
+  }
+  fclose(f);
+  if (!found) return false;
+  c->hop_variant = hv;
+  c->gram_variant = gv;
+  c->update_variant = uv;
+  bms_set_hop_config(c, BMS_PREC_F64, h64);
+  bms_set_hop_config(c, BMS_PREC_F32, h32);
+  return true;
+}
+
+void cache_append(bms_ctx* c, const std::string& key, const double* us) {
+  FILE* f = fopen(c->tune_cache.c_str(), "a");
+  if (!f) return;
+  const HopCfg& a = c->hop_cfg[0];
+  const HopCfg& b = c->hop_cfg[1];
+  fprintf(f,
+          "{\"key\": \"%s\", \"hop\": %d, \"gram\": %d, \"update\": %d, \"hop_f64\": [%d, %d, %d, "
+          "%d, %d], \"hop_f32\": [%d, %d, %d, %d, %d], \"hop_pair_us\": [%.1f, %.1f]}\n",
+          key.c_str(), c->hop_variant, c->gram_variant, c->update_variant, a.ty, a.tz, a.tt, a.cap,
+          a.nt, b.ty, b.tz, b.tt, b.cap, b.nt, us[0], us[1]);
+  fclose(f);
+}
+
+}  // namespace
+
 extern "C" int bms_autotune(bms_ctx* c, double mass, int n, int ns, const double* shifts,
                             int precision, int iters, const void* B, void* X) {
   if (!c) return BMS_EINVAL;
@@ -57,8 +206,19 @@ extern "C" int bms_autotune(bms_ctx* c, double mass, int n, int ns, const double
   o.precision = precision;
   o.max_refine = 0;
   o.reliable_interval = 1 << 30;  // time the iteration kernels only
+  int rc = solve_validate(c, mass, n, ns, shifts, 0.5, iters, &o, B, X);
+  if (rc) return rc;
+  if ((rc = ensure_device(c))) return rc;
+  const std::string key = tune_key(c, n, ns, precision);
+  if (!c->tune_cache.empty() && cache_lookup(c, key)) return BMS_OK;
+  // 1. the hop's kernel and traversal, per precision the solve uses
+  double hop_us[2] = {0, 0};
+  if ((rc = stream_begin(c))) return rc;
+  if ((rc = tune_hop(c, n, true, &hop_us[0]))) return rc;
+  if (precision == BMS_PREC_MIXED && (rc = tune_hop(c, n, false, &hop_us[1]))) return rc;
+  // 2. the Gram and update kernels, timed inside real block iterations
   const bool timing_was = c->timing;
-  const int kinds[3] = {BMS_KERNEL_HOP, BMS_KERNEL_GRAM, BMS_KERNEL_UPDATE};
+  const int kinds[2] = {BMS_KERNEL_GRAM, BMS_KERNEL_UPDATE};
   for (int kind : kinds) {
     int* slot = variant_slot(c, kind);
     std::vector<int> cand = candidates(kind, n);
@@ -70,7 +230,7 @@ extern "C" int bms_autotune(bms_ctx* c, double mass, int n, int ns, const double
       bms_stats st;
       memset(&st, 0, sizeof st);
       // a target far below reach: exactly `iters` iterations are run
-      int rc = bms_solve(c, mass, n, ns, shifts, 1e-300, iters, &o, B, X, &st);
+      rc = bms_solve(c, mass, n, ns, shifts, 1e-300, iters, &o, B, X, &st);
       if (rc != BMS_OK && rc != BMS_ENOCONV && rc != BMS_EBREAKDOWN && rc != BMS_ENAN) {
         bms_timing_enable(c, timing_was);
         c->timing = timing_was;
@@ -88,7 +248,8 @@ extern "C" int bms_autotune(bms_ctx* c, double mass, int n, int ns, const double
   }
   bms_timing_enable(c, timing_was);
   c->timing = timing_was;
-  return BMS_OK;
+  if (!c->tune_cache.empty()) cache_append(c, key, hop_us);
+  return stream_end(c);
 }
 
 extern "C" int bms_solve_batch(int nprob, bms_ctx* const* ctxs, const double* mass, const int* n,

@@ -55,6 +55,24 @@ __global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restri
   }
 }
 
+// A link element, loaded with the non-temporal hint when NT (the links are
+// read once per half hop; the hint keeps them from displacing the input
+// block's neighbour columns in L2).
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ double2 link_ld(const double2* p) {
+  if (!NT) return *p;
+  const d2v v = __builtin_nontemporal_load((const d2v*)p);
+  return make_double2(v.x, v.y);
+}
+template <bool NT>
+__device__ __forceinline__ float2 link_ld(const float2* p) {
+  if (!NT) return *p;
+  const f2v v = __builtin_nontemporal_load((const f2v*)p);
+  return make_float2(v.x, v.y);
+}
+
 // Tiled traversal. A tile is hx x ty x tz x tt checkerboard sites (whole
 // x-rows); the tiles of one (y, z) pencil are walked along t. Work-groups go
 // to the 8 XCDs in turn (work-group b to XCD b % 8); XCD x takes pencils x,
@@ -97,7 +115,7 @@ __device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom
 // neighbouring columns) and a wave touches as few cache lines as the bytes
 // allow. In FP32 a thread's R columns are consecutive instead (g*R .. g*R+R-1),
 // which the compiler loads as 16-byte vectors.
-template <typename T, int R>
+template <typename T, int R, bool NT>
 __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ links,
                                                 const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out,
@@ -137,7 +155,7 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
     const C* L = links + link_off(s, k, 0, sbl);
     C l[9], v[3][R];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) l[e] = L[e * st];
+    for (int e = 0; e < 9; ++e) l[e] = link_ld<NT>(L + e * st);
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
@@ -182,7 +200,7 @@ __device__ __forceinline__ double quad_bcast(double v) {
 // element e reaches the other three threads of the quad by a DPP broadcast
 // from lane e % 4. Columns as in k_hop (interleaved in FP64, consecutive in
 // FP32).
-template <typename T, int R>
+template <typename T, int R, bool NT>
 __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ links,
                                                   const cplx<T>* __restrict__ in,
                                                   cplx<T>* __restrict__ out,
@@ -216,7 +234,8 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
     const int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
     const C* src = in + (size_t)nb * 3 * n + j0;
     const C* L = links + link_off(s, k, 0, sbl);
-    const C t0 = L[q * st], t1 = L[(q + 4) * st], t2 = L[e2 * st];
+    const C t0 = link_ld<NT>(L + q * st), t1 = link_ld<NT>(L + (q + 4) * st),
+            t2 = link_ld<NT>(L + e2 * st);
     C v[3][R];
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb)
@@ -283,6 +302,44 @@ static HopTiles hop_tiles(const bms_ctx* c, int spb, int ty, int tz, int tt) {
   return m;
 }
 
+bool hop_tiling_valid(const bms_ctx* c, int n, int ty, int tz, int tt) {
+  const bool quad = n == 4 || n == 8 || n == 16 || n == 32;
+  const int R = (n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1);
+  const int spb = quad ? BMS_WG / 4 : (BMS_WG % (n / R) == 0 ? BMS_WG / (n / R) : 0);
+  return spb > 0 && hop_tiles(c, spb, ty, tz, tt).on != 0;
+}
+
+// LDS a hop work-group reserves (and leaves unused) so that at most `cap`
+// are resident per compute unit; 0 when that would exceed one work-group's
+// limit (the cap is then not applied).
+size_t hop_cap_lds(const bms_ctx* c, int cap) {
+  if (cap <= 0 || c->lds_per_cu <= 0) return 0;
+  const size_t lds = (size_t)c->lds_per_cu / (cap + 1) + 1;
+  return c->lds_per_block > 0 && lds > (size_t)c->lds_per_block ? 0 : lds;
+}
+
+// The traversal of one half hop for this context, block width and precision.
+HopPlan hop_plan(const bms_ctx* c, int n, bool fp64) {
+  HopPlan p;
+  const HopCfg& hc = c->hop_cfg[fp64 ? 0 : 1];
+  const int hv = c->hop_variant;
+  p.quad = (n == 4 || n == 8 || n == 16 || n == 32) && (hv == 1 || hv == 3 || hv < 0);
+  // tile extents: the configured ones, else 8 x 8 x 4; tiled for variants 2
+  // and 3, or by the configuration (ty > 0; ty = 0 keeps the natural order),
+  // or by default in FP64 at n >= 16
+  const bool tiled_default = fp64 && n >= 16;
+  p.tiled = hv == 2 || hv == 3 || (hv < 0 && (hc.ty > 0 || (hc.ty < 0 && tiled_default)));
+  p.ty = hc.ty > 0 ? hc.ty : 8;
+  p.tz = hc.ty > 0 ? hc.tz : 8;
+  p.tt = hc.ty > 0 ? hc.tt : 4;
+  // At most `cap` resident work-groups per compute unit (by reserving LDS the
+  // kernel does not use): fewer sites in flight keep the neighbours' re-reads
+  // inside each XCD's L2 (at 32^4 FP64 n = 16 513 -> 455 us natural order).
+  p.cap = hc.cap >= 0 ? hc.cap : (n >= 16 ? 2 : (n == 8 ? 3 : 0));
+  p.nt = hc.nt > 0;
+  return p;
+}
+
 template <typename T>
 hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
                       double a, double b, const int* skip) {
@@ -291,32 +348,30 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
   // Variants: 0 one thread per (site, column group), 1 four threads per site
   // sharing the links (n = 4, 8, 16, 32), 2 and 3 the same in the tiled
-  // traversal; the default is 1, tiled in FP64 at n >= 16. Measured at 32^4,
-  // one half hop: FP64 n = 16 415 us (tiled) / 453 (natural), FP32 n = 16 246,
-  // FP64 n = 8 259, FP32 n = 8 162 (quad kernel).
-  const int hv = c->hop_variant;
-  const bool quad_ok = n == 4 || n == 8 || n == 16 || n == 32;
-  const bool quad = quad_ok && (hv == 1 || hv == 3 || hv < 0);
-  const bool tiled = hv == 2 || hv == 3 || (hv < 0 && sizeof(T) == 8 && n >= 16);
-  // At most `cap` resident work-groups per compute unit, by reserving LDS the
-  // kernel does not use: fewer sites in flight keep the neighbours' re-reads
-  // inside each XCD's L2 (at 32^4 FP64 n = 16 513 -> 455 us natural order).
-  const int cap = n >= 16 ? 2 : (n == 8 ? 3 : 0);
-  const size_t lds = cap > 0 && c->lds_per_cu > 0 ? (size_t)c->lds_per_cu / (cap + 1) + 1 : 0;
-  constexpr int kTy = 8, kTz = 8, kTt = 4;  // tile extent in y, z, t
-  if (quad) {
+  // traversal; the default is 1, tiled in FP64 at n >= 16. The traversal's
+  // tile extents, resident cap and link-load hint come from the context's
+  // hop configuration (bms_set_hop_config, bms_autotune).
+  const HopPlan hp = hop_plan(c, n, sizeof(T) == 8);
+  const size_t lds = hop_cap_lds(c, hp.cap);
+  if (hp.quad) {
     dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);
-    HopTiles tiles = tiled ? hop_tiles(c, BMS_WG / 4, kTy, kTz, kTt) : HopTiles{};
-#define HOPQ(RR)                                                                           \
-  k_hop_q<T, RR><<<qgrid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out, \
-                                                 (const cplx<T>*)aux, (T)a, (T)b, c->geom, \
-                                                 n, par, c->sbl, skip, tiles)
+    HopTiles tiles = hp.tiled ? hop_tiles(c, BMS_WG / 4, hp.ty, hp.tz, hp.tt) : HopTiles{};
+#define HOPQ(RR, NT)                                                                       \
+  k_hop_q<T, RR, NT><<<qgrid, BMS_WG, lds, c->stream>>>(                                   \
+      links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom,  \
+      n, par, c->sbl, skip, tiles)
+#define HOPQN(RR) \
+  if (hp.nt)      \
+    HOPQ(RR, true); \
+  else            \
+    HOPQ(RR, false)
     switch (n) {
-      case 4: HOPQ(1); break;
-      case 8: HOPQ(2); break;
-      case 16: HOPQ(4); break;
-      default: HOPQ(8);
+      case 4: HOPQN(1); break;
+      case 8: HOPQN(2); break;
+      case 16: HOPQN(4); break;
+      default: HOPQN(8);
     }
+#undef HOPQN
 #undef HOPQ
     return hipGetLastError();
   }
@@ -325,18 +380,26 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   uint32_t nthr = (uint32_t)c->vh * ngrp;
   dim3 grid((nthr + BMS_WG - 1) / BMS_WG);
   FastDiv dg = make_fastdiv(ngrp);
-  HopTiles tiles = tiled && BMS_WG % ngrp == 0 ? hop_tiles(c, BMS_WG / (int)ngrp, kTy, kTz, kTt)
-                                               : HopTiles{};
-#define HOP_LAUNCH(RR)                                                                     \
-  k_hop<T, RR><<<grid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in, (cplx<T>*)out,    \
-                                              (const cplx<T>*)aux, (T)a, (T)b, c->geom, n, \
-                                              dg, par, c->sbl, skip, tiles)
+  HopTiles tiles = hp.tiled && BMS_WG % ngrp == 0
+                       ? hop_tiles(c, BMS_WG / (int)ngrp, hp.ty, hp.tz, hp.tt)
+                       : HopTiles{};
+#define HOP_LAUNCH(RR, NT)                                                                 \
+  k_hop<T, RR, NT><<<grid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in,            \
+                                                  (cplx<T>*)out, (const cplx<T>*)aux, (T)a, \
+                                                  (T)b, c->geom, n, dg, par, c->sbl, skip, \
+                                                  tiles)
+#define HOPN(RR)        \
+  if (hp.nt)            \
+    HOP_LAUNCH(RR, true); \
+  else                  \
+    HOP_LAUNCH(RR, false)
   if (R == 4)
-    HOP_LAUNCH(4);
+    HOPN(4);
   else if (R == 2)
-    HOP_LAUNCH(2);
+    HOPN(2);
   else
-    HOP_LAUNCH(1);
+    HOPN(1);
+#undef HOPN
 #undef HOP_LAUNCH
   return hipGetLastError();
 }

@@ -75,6 +75,20 @@ enum {
   PP_DRAIN = 4,  // frozen with an increment pending: X += P_k-1 Mxd
 };
 
+// Traversal of the half hop for one precision: tiles of whole x-rows ty x tz
+// x tt in y, z, t (ty = 0: natural order; -1: the built-in choice for every
+// field), at most `cap` resident work-groups per compute unit (0: no cap;
+// -1: built-in by block width), non-temporal link loads (nt = 1).
+struct HopCfg {
+  int ty = -1, tz = 8, tt = 4;
+  int cap = -1;
+  int nt = 0;
+};
+struct HopPlan {
+  bool quad = false, tiled = false, nt = false;
+  int ty = 8, tz = 8, tt = 4, cap = 0;
+};
+
 struct bms_ctx {
   int dims[4];
   int bc[4];
@@ -89,6 +103,7 @@ struct bms_ctx {
   int device = -1;
   int num_cu = 0;  // compute units of the device (set with the stream)
   int lds_per_cu = 0;  // bytes of LDS per compute unit (set with the stream)
+  int lds_per_block = 0;  // bytes of LDS one work-group may take
   bool gauge_set = false;
   DevBuf links64, links32;  // [parity][blocked links] complex
   std::vector<DevBuf> scratch;  // named by slot index
@@ -98,6 +113,8 @@ struct bms_ctx {
   int gram_variant = -1;
   int hop_variant = -1;
   int force_variant = -1;  // 0: D_oe hops per shift + per-link kernel; else fused
+  HopCfg hop_cfg[2];       // [0] FP64, [1] FP32 blocks
+  std::string tune_cache;  // bms_autotune's cache file ("" = none)
   // per-kernel timing (bms_timing_enable)
   bool timing = false;
   double kt_ms[BMS_NKERNELS] = {0};
@@ -126,6 +143,9 @@ int ensure_device(bms_ctx* c);
 int ensure_buf(bms_ctx* c, DevBuf& b, size_t bytes);
 int scratch_buf(bms_ctx* c, int slot, size_t bytes, void** p);
 int stream_begin(bms_ctx* c);
+// the host-side argument checks of bms_solve (BMS_OK or the error it returns)
+int solve_validate(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
+                   int max_iter, const bms_opts* o, const void* B, const void* X);
 // size every workspace slot a solve of this shape may use (see solver.cpp)
 int solve_reserve(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
                   int max_iter, const bms_opts* opts, const void* B, const void* X);
@@ -136,6 +156,10 @@ hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void*
 
 // out = b * D_{par} in  (+ a * aux if aux)  on n columns; done = optional
 // device flag (skip if *done)
+HopPlan hop_plan(const bms_ctx* c, int n, bool fp64);
+size_t hop_cap_lds(const bms_ctx* c, int cap);
+// whether ty x tz x tt tiles of whole x-rows divide this lattice for block width n
+bool hop_tiling_valid(const bms_ctx* c, int n, int ty, int tz, int tt);
 template <typename T>
 hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
                       double a, double b, const int* skip);

@@ -244,6 +244,7 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
     const void* p[16];
     double mass;
     int K, n, ns, nb, hop_v, gram_v, upd_v, prec;
+    HopCfg hop_cfg[2];
     SmallParams sp;
     SmallState sm;
   } k;
@@ -260,6 +261,8 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
   k.gram_v = c->gram_variant;
   k.upd_v = c->update_variant;
   k.prec = (int)sizeof(T);
+  k.hop_cfg[0] = c->hop_cfg[0];
+  k.hop_cfg[1] = c->hop_cfg[1];
   k.sp = sp;
   k.sm = w.sm;
   return std::string((const char*)&k, sizeof k);
@@ -546,6 +549,11 @@ static int validate_solve(bms_ctx* c, double mass, int n, int ns, const double* 
   }
   if (!c->gauge_set) return set_err(c, BMS_ESTATE, "no gauge field set");
   return BMS_OK;
+}
+
+int solve_validate(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
+                   int max_iter, const bms_opts* o, const void* B, const void* X) {
+  return validate_solve(c, mass, n, ns, shifts, tol, max_iter, o, B, X);
 }
 
 // x = G^-1 b for Hermitian positive definite G (n x n, row-major) and n
