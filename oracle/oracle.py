@@ -49,6 +49,14 @@ def lib():
                                ctypes.c_double, ctypes.c_int, dp]
         L.ora_mscg.restype = ctypes.c_int
         L.ora_force.argtypes = [ip, ip, dp, ctypes.c_int, dp, dp, dp]
+        L.ora_dslash_half_imp.argtypes = [ip, ip, dp, dp, ctypes.c_int, dp, dp]
+        L.ora_mdagm_imp.argtypes = [ip, ip, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.ora_cg_imp.argtypes = [ip, ip, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp,
+                                 ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.ora_cg_imp.restype = ctypes.c_int
+        L.ora_mscg_imp.argtypes = [ip, ip, dp, dp, ctypes.c_double, ctypes.c_int, dp, dp, dp,
+                                   ctypes.c_double, ctypes.c_int, dp]
+        L.ora_mscg_imp.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -72,28 +80,41 @@ def vol(dims):
 
 # ---- operator --------------------------------------------------------------
 
-def dslash_half(dims, bc, U, par_out, v):
-    """(D v) on sites of parity par_out; v is a half vector [Vh][3]."""
+def dslash_half(dims, bc, U, par_out, v, W=None):
+    """(D v) on sites of parity par_out; v is a half vector [Vh][3]. With W
+    (three-hop links [mu][idx][3][3]) the improved operator, U then being the
+    one-hop links."""
     U = _c(U)
     v = _c(v)
     out = np.empty_like(v)
-    lib().ora_dslash_half(_i4(dims), _i4(bc), _ptr(U), int(par_out), _ptr(v), _ptr(out))
+    if W is None:
+        lib().ora_dslash_half(_i4(dims), _i4(bc), _ptr(U), int(par_out), _ptr(v), _ptr(out))
+    else:
+        W = _c(W)
+        lib().ora_dslash_half_imp(_i4(dims), _i4(bc), _ptr(U), _ptr(W), int(par_out), _ptr(v),
+                                  _ptr(out))
     return out
 
 
-def mdagm(dims, bc, U, mass, sigma, v):
+def mdagm(dims, bc, U, mass, sigma, v, W=None):
     """(A + sigma) v, A = m^2 - D_eo D_oe; v is [Vh][3] or a block [Vh][3][n]."""
     U = _c(U)
     v = _c(v)
     if v.ndim == 3:
-        return np.stack([mdagm(dims, bc, U, mass, sigma, v[..., j]) for j in range(v.shape[2])],
-                        axis=-1)
+        return np.stack([mdagm(dims, bc, U, mass, sigma, v[..., j], W)
+                         for j in range(v.shape[2])], axis=-1)
     out = np.empty_like(v)
-    lib().ora_mdagm(_i4(dims), _i4(bc), _ptr(U), float(mass), float(sigma), _ptr(v), _ptr(out))
+    if W is None:
+        lib().ora_mdagm(_i4(dims), _i4(bc), _ptr(U), float(mass), float(sigma), _ptr(v),
+                        _ptr(out))
+    else:
+        W = _c(W)
+        lib().ora_mdagm_imp(_i4(dims), _i4(bc), _ptr(U), _ptr(W), float(mass), float(sigma),
+                            _ptr(v), _ptr(out))
     return out
 
 
-def dense_operator(dims, bc, U, mass, sigma):
+def dense_operator(dims, bc, U, mass, sigma, W=None):
     """Explicit matrix of (A + sigma) on the 3*Vh-dimensional even-site space."""
     n = vol(dims) // 2 * 3
     A = np.empty((n, n), dtype=np.complex128)
@@ -101,24 +122,29 @@ def dense_operator(dims, bc, U, mass, sigma):
     for k in range(n):
         e[:] = 0
         e[k] = 1
-        A[:, k] = mdagm(dims, bc, U, mass, sigma, e.reshape(-1, 3)).reshape(-1)
+        A[:, k] = mdagm(dims, bc, U, mass, sigma, e.reshape(-1, 3), W).reshape(-1)
     return A
 
 
 # ---- solvers ---------------------------------------------------------------
 
-def cg(dims, bc, U, mass, sigma, b, tol=1e-13, maxiter=100000):
+def cg(dims, bc, U, mass, sigma, b, tol=1e-13, maxiter=100000, W=None):
     """Plain CG for one half vector. Returns (x, iterations, true relative residual)."""
     U = _c(U)
     b = _c(b)
     x = np.empty_like(b)
     tr = ctypes.c_double(0)
-    k = lib().ora_cg(_i4(dims), _i4(bc), _ptr(U), float(mass), float(sigma), _ptr(b), _ptr(x),
-                     float(tol), int(maxiter), ctypes.byref(tr))
+    if W is None:
+        k = lib().ora_cg(_i4(dims), _i4(bc), _ptr(U), float(mass), float(sigma), _ptr(b), _ptr(x),
+                         float(tol), int(maxiter), ctypes.byref(tr))
+    else:
+        W = _c(W)
+        k = lib().ora_cg_imp(_i4(dims), _i4(bc), _ptr(U), _ptr(W), float(mass), float(sigma),
+                             _ptr(b), _ptr(x), float(tol), int(maxiter), ctypes.byref(tr))
     return x, k, tr.value
 
 
-def mscg(dims, bc, U, mass, shifts, b, tol=1e-13, maxiter=100000):
+def mscg(dims, bc, U, mass, shifts, b, tol=1e-13, maxiter=100000, W=None):
     """Multi-shift CG for one half vector and ascending shifts.
 
     Returns (x[nshift][Vh][3], iterations, true relative residual per shift)."""
@@ -129,12 +155,18 @@ def mscg(dims, bc, U, mass, shifts, b, tol=1e-13, maxiter=100000):
     b = _c(b)
     x = np.empty((len(shifts),) + b.shape, dtype=np.complex128)
     tr = np.zeros(len(shifts))
-    k = lib().ora_mscg(_i4(dims), _i4(bc), _ptr(U), float(mass), len(shifts), _ptr(shifts),
-                       _ptr(b), _ptr(x), float(tol), int(maxiter), _ptr(tr))
+    if W is None:
+        k = lib().ora_mscg(_i4(dims), _i4(bc), _ptr(U), float(mass), len(shifts), _ptr(shifts),
+                           _ptr(b), _ptr(x), float(tol), int(maxiter), _ptr(tr))
+    else:
+        W = _c(W)
+        k = lib().ora_mscg_imp(_i4(dims), _i4(bc), _ptr(U), _ptr(W), float(mass), len(shifts),
+                               _ptr(shifts), _ptr(b), _ptr(x), float(tol), int(maxiter),
+                               _ptr(tr))
     return x, k, tr
 
 
-def solve_block(dims, bc, U, mass, shifts, B, tol=1e-13, maxiter=100000):
+def solve_block(dims, bc, U, mass, shifts, B, tol=1e-13, maxiter=100000, W=None):
     """X[s] = (A + shifts[s])^-1 B for a block B[Vh][3][n], any shift order.
 
     Returns (X[nshift][Vh][3][n], true relative residual [nshift][n])."""
@@ -144,18 +176,18 @@ def solve_block(dims, bc, U, mass, shifts, B, tol=1e-13, maxiter=100000):
     X = np.empty((len(shifts),) + B.shape, dtype=np.complex128)
     res = np.empty((len(shifts), n))
     for j in range(n):
-        x, _, tr = mscg(dims, bc, U, mass, shifts[order], B[..., j], tol, maxiter)
+        x, _, tr = mscg(dims, bc, U, mass, shifts[order], B[..., j], tol, maxiter, W)
         X[order, ..., j] = x
         res[order, j] = tr
     return X, res
 
 
-def true_residuals(dims, bc, U, mass, shifts, B, X):
+def true_residuals(dims, bc, U, mass, shifts, B, X, W=None):
     """|b_i - (A + s) x_i| / |b_i| for every shift s and column i (FP64)."""
     res = np.empty((len(shifts), B.shape[2]))
     bn = np.linalg.norm(B.reshape(-1, B.shape[2]), axis=0)
     for s, sig in enumerate(shifts):
-        r = B - mdagm(dims, bc, U, mass, sig, X[s])
+        r = B - mdagm(dims, bc, U, mass, sig, X[s], W)
         res[s] = np.linalg.norm(r.reshape(-1, B.shape[2]), axis=0) / np.where(bn > 0, bn, 1)
     return res
 
