@@ -224,6 +224,47 @@ def force_measure(bms, torch, np, configs, reps=3):
                 hops_then_per_link_us=round(res[0][0], 1))
 
 
+def operator_block_gain(bms, torch, dims, Ud, reps=5):
+    """Half hops on one GPU for the unimproved operator (8 links per site)
+    and the improved one (one-hop plus three-hop links, 16 per site; V = 9/8 U,
+    W = -1/24 U, the cost does not depend on the values): time per hop at
+    n = 16 and n = 1 in FP64 and FP32, algorithmic GB/s at n = 16, and the
+    block gain per column, 16 x t(n=1) / t(n=16)."""
+    vh = Ud.shape[1] // 2
+    out = {}
+    for name in ("unimproved", "improved"):
+        ctx = bms.Context(dims, (1, 1, 1, -1))
+        if name == "improved":
+            ctx.set_gauge_improved(Ud * (9.0 / 8.0), Ud * (-1.0 / 24.0))
+        else:
+            ctx.set_gauge(Ud)
+        nl = 16 if name == "improved" else 8
+        res = {}
+        for prec, dt, b in ((bms.BMS_PREC_F64, torch.complex128, 8),
+                            (bms.BMS_PREC_F32, torch.complex64, 4)):
+            t = {}
+            for n in (1, 16):
+                x = torch.zeros((vh, 3, n), dtype=dt, device="cuda")
+                y = ctx.apply_hop(1, x, prec)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    y = ctx.apply_hop(1, x, prec)
+                e1.record()
+                torch.cuda.synchronize()
+                t[n] = e0.elapsed_time(e1) * 1e3 / reps
+            algo = vh * nl * 9 * 2 * b + 2 * vh * 3 * 16 * 2 * b
+            res["f64" if b == 8 else "f32"] = dict(
+                us_n16=round(t[16], 1), us_n1=round(t[1], 1),
+                gbs_n16=round(algo / (t[16] * 1e-6) / 1e9, 1),
+                block_gain_per_column=round(16 * t[1] / t[16], 2))
+        out[name] = res
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +287,8 @@ def main():
                          "(median, min, max reported aside)")
     ap.add_argument("--no-force", action="store_true",
                     help="skip the force-kernel measurement (reported aside)")
+    ap.add_argument("--no-operators", action="store_true",
+                    help="skip the unimproved/improved operator comparison (reported aside)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -398,6 +441,11 @@ def main():
                      note="first: the timed seed (mean of the timed steps); others: one solve each")
         log("bench: seeds %s" % (seeds,))
 
+    operators = None
+    if not args.no_operators:
+        operators = operator_block_gain(bms, torch, dims, Ud)
+        log("bench: operators %s" % (operators,))
+
     force = None
     if not args.no_force:
         force = force_measure(bms, torch, np, configs)
@@ -441,6 +489,7 @@ def main():
         seeds=seeds,
         action=action,
         force=force,
+        operators=operators,
         per_vector=dict(value=round(pv_rate, 4) if pv_rate == pv_rate else None,
                         unit="RHS-solves/s", columns=args.baseline_cols,
                         iterations=pv_iters, dtype="f64"),

@@ -144,6 +144,24 @@ int bms_destroy(bms_ctx* ctx);
 int bms_set_gauge(bms_ctx* ctx, const void* U);
 
 /*
+ * Load the links of the improved, less local staggered operator (the
+ * paper's outlook, Sec. V, expects a less local operator to gain more from
+ * reading each link once per block): one-hop links V and three-hop links W,
+ * both device pointers in the layout of U, the improvement coefficients
+ * folded in by the caller (e.g. V = 9/8 x fat links, W = -1/24 x long links
+ * for the Naik term):
+ *   (D psi)(x) = 1/2 sum_mu eta_mu(x) [ V_mu(x) psi(x+mu) - V_mu(x-mu)^dag psi(x-mu)
+ *                                     + W_mu(x) psi(x+3mu) - W_mu(x-3mu)^dag psi(x-3mu) ]
+ * with the boundary factor bc[mu] on every link or three-hop link that
+ * crosses the lattice boundary. Every later bms_apply_hop, bms_apply_mdagm,
+ * bms_solve, bms_rational_apply and bms_autotune acts with it (16 links per
+ * site and half hop) until bms_set_gauge loads unimproved links; bms_force
+ * then returns BMS_EINVAL. Errors: BMS_EINVAL for NULL pointers or an extent
+ * below 4.
+ */
+int bms_set_gauge_improved(bms_ctx* ctx, const void* V, const void* W);
+
+/*
  * out = D_{parity_out, 1-parity_out} in: the half hop from sites of parity
  * 1-parity_out to sites of parity parity_out (parity_out = 1 gives D_oe,
  * 0 gives D_eo) on n columns. precision BMS_PREC_F64 or BMS_PREC_F32 selects

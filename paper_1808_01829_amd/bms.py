@@ -45,7 +45,7 @@ EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create
            "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant",
            "bms_get_variant", "bms_autotune", "bms_solve_batch", "bms_action_noalloc",
            "bms_rational_apply", "bms_set_hop_config", "bms_get_hop_config",
-           "bms_set_tune_cache"]
+           "bms_set_tune_cache", "bms_set_gauge_improved"]
 
 
 class bms_opts(ctypes.Structure):
@@ -101,6 +101,7 @@ def _lib():
         L.bms_create.argtypes = [ctypes.POINTER(vp), ip, ip, vp]
         L.bms_destroy.argtypes = [vp]
         L.bms_set_gauge.argtypes = [vp, vp]
+        L.bms_set_gauge_improved.argtypes = [vp, vp, vp]
         L.bms_apply_hop.argtypes = [vp, i, i, vp, vp, i]
         L.bms_apply_mdagm.argtypes = [vp, d, d, i, vp, vp, i]
         L.bms_solve.argtypes = [vp, d, i, i, dp, d, i, ctypes.POINTER(bms_opts), vp, vp,
@@ -186,6 +187,10 @@ def bms_destroy(ctx):
 
 def bms_set_gauge(ctx, U):
     _check(ctx, _lib().bms_set_gauge(ctx, _ptr(U)))
+
+
+def bms_set_gauge_improved(ctx, V, W):
+    _check(ctx, _lib().bms_set_gauge_improved(ctx, _ptr(V), _ptr(W)))
 
 
 def bms_apply_hop(ctx, parity_out, n, inp, out, precision=BMS_PREC_F64):
@@ -364,6 +369,14 @@ class Context:
         import torch
         assert U.dtype == torch.complex128 and tuple(U.shape) == (4, self.vol, 3, 3)
         bms_set_gauge(self.h, U)
+
+    def set_gauge_improved(self, V, W):
+        """One-hop links V and three-hop links W of the improved operator
+        (coefficients folded in), both shaped like U."""
+        import torch
+        for F in (V, W):
+            assert F.dtype == torch.complex128 and tuple(F.shape) == (4, self.vol, 3, 3)
+        bms_set_gauge_improved(self.h, V, W)
 
     def _block(self, v, dtype):
         assert v.dtype == dtype and v.dim() == 3 and v.shape[0] == self.vh and v.shape[1] == 3, \

@@ -164,6 +164,26 @@ extern "C" int bms_set_gauge(bms_ctx* c, const void* U) {
   HIP_TRY(c, launch_fill_zero(c->stream, c->links64.p, nlink * sizeof(double2)));
   HIP_TRY(c, launch_fill_zero(c->stream, c->links32.p, nlink * sizeof(float2)));
   HIP_TRY(c, launch_gauge_import(c, U, c->links64.p, c->links32.p));
+  c->nlinks = 8;
+  c->gauge_set = true;
+  return stream_end(c);
+}
+
+extern "C" int bms_set_gauge_improved(bms_ctx* c, const void* V, const void* W) {
+  if (!c) return BMS_EINVAL;
+  if (!V || !W) return set_err(c, BMS_EINVAL, "bms_set_gauge_improved: V or W is NULL");
+  for (int i = 0; i < 4; ++i)
+    if (c->dims[i] < 4)
+      return set_err(c, BMS_EINVAL, "the improved operator needs every extent >= 4");
+  int rc = stream_begin(c);
+  if (rc) return rc;
+  size_t nlink = (size_t)2 * c->nblk * 144 << c->sbl;
+  if ((rc = ensure_buf(c, c->links64, nlink * sizeof(double2)))) return rc;
+  if ((rc = ensure_buf(c, c->links32, nlink * sizeof(float2)))) return rc;
+  HIP_TRY(c, launch_fill_zero(c->stream, c->links64.p, nlink * sizeof(double2)));
+  HIP_TRY(c, launch_fill_zero(c->stream, c->links32.p, nlink * sizeof(float2)));
+  HIP_TRY(c, launch_gauge_import_improved(c, V, W, c->links64.p, c->links32.p));
+  c->nlinks = 16;
   c->gauge_set = true;
   return stream_end(c);
 }

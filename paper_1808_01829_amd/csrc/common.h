@@ -138,22 +138,25 @@ __device__ __forceinline__ SiteCoord site_coords(uint32_t s, const Geom& g, int 
   return c;
 }
 
-// cb index of the neighbour in direction mu (0..3), dir +1 / -1
+// cb index of the neighbour in direction mu (0..3) at distance dir (+-1, or
+// +-3 for the three-hop links of the improved operator; |dir| <= L_mu)
 __device__ __forceinline__ int neighbour_cb(int s, const SiteCoord& c, const Geom& g, int mu, int dir) {
   if (mu == 0) {
     int xn = c.x + dir;
-    xn = xn < 0 ? g.L[0] - 1 : (xn >= g.L[0] ? 0 : xn);
+    xn = xn < 0 ? xn + g.L[0] : (xn >= g.L[0] ? xn - g.L[0] : xn);
     return s - c.xh + (xn >> 1);
   }
   int v = mu == 1 ? c.y : (mu == 2 ? c.z : c.t);
   int vn = v + dir;
-  vn = vn < 0 ? g.L[mu] - 1 : (vn >= g.L[mu] ? 0 : vn);
+  vn = vn < 0 ? vn + g.L[mu] : (vn >= g.L[mu] ? vn - g.L[mu] : vn);
   return s + (vn - v) * g.stride[mu];
 }
 
 // Links of one output parity, blocked structure-of-arrays:
-// link k (0..3 forward mu=k, 4..7 backward mu=k-4) element e (0..8, row-major)
-// of checkerboard site s lives at ((s>>sbl)*72 + k*9 + e) << sbl | (s & (SB-1)).
-__device__ __forceinline__ size_t link_off(uint32_t s, int k, int e, int sbl) {
-  return ((((size_t)(s >> sbl)) * 72 + k * 9 + e) << sbl) | (s & ((1u << sbl) - 1));
+// link k (0..3 forward mu=k, 4..7 backward mu=k-4; for the improved operator
+// also 8..11 three-hop forward, 12..15 three-hop backward) element e (0..8,
+// row-major) of checkerboard site s lives at
+// ((s>>sbl)*per + k*9 + e) << sbl | (s & (SB-1)), per = 9 * links per site.
+__device__ __forceinline__ size_t link_off(uint32_t s, int k, int e, int sbl, int per = 72) {
+  return ((((size_t)(s >> sbl)) * per + k * 9 + e) << sbl) | (s & ((1u << sbl) - 1));
 }

@@ -378,6 +378,8 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   for (int s = 0; s < ns; ++s)
     if (!std::isfinite(alpha[s])) return set_err(c, BMS_EINVAL, "alpha[%d] not finite", s);
   if (!c->gauge_set) return set_err(c, BMS_ESTATE, "no gauge field set");
+  if (c->nlinks != 8)
+    return set_err(c, BMS_EINVAL, "the force is defined for the unimproved operator only");
   int rc;
   if ((rc = stream_begin(c))) return rc;
   const size_t blk = (size_t)c->vh * 3 * n;

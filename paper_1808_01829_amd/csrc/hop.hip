@@ -55,6 +55,63 @@ __global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restri
   }
 }
 
+// Signed distance of hop k: one step forward (0..3) and back (4..7), for the
+// improved operator three steps forward (8..11) and back (12..15).
+__device__ __forceinline__ int hop_dist(int k) {
+  return k < 4 ? 1 : (k < 8 ? -1 : (k < 12 ? 3 : -3));
+}
+
+// The improved operator (all extents >= 4): per output parity p and cb site
+// s the 16 links of its half hop,
+//   k = mu      :  +1/2 eta_mu(x) bf  V_mu(x)                (to x + mu)
+//   k = 4 + mu  :  -1/2 eta_mu(x) bb  V_mu(x - mu)^dag       (to x - mu)
+//   k = 8 + mu  :  +1/2 eta_mu(x) b3f W_mu(x)                (to x + 3 mu)
+//   k = 12 + mu :  -1/2 eta_mu(x) b3b W_mu(x - 3 mu)^dag     (to x - 3 mu)
+// b3f = bc[mu] when x + 3 mu wraps (x_mu >= L_mu - 3), b3b when x - 3 mu
+// wraps (x_mu < 3): with L_mu >= 4 a three-hop wraps at most once.
+__global__ __launch_bounds__(BMS_WG) void k_gauge_import_improved(
+    const double2* __restrict__ V, const double2* __restrict__ W, double2* __restrict__ l64,
+    float2* __restrict__ l32, Geom g, Bc bc, int sbl, int nblk, int vol) {
+  uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
+  if (tid >= 2u * (uint32_t)g.vh) return;
+  const int par = tid >= (uint32_t)g.vh;
+  const uint32_t s = tid - (par ? g.vh : 0);
+  const int per = 9 * 16;
+  SiteCoord c = site_coords(s, g, par);
+  int co[4] = {c.x, c.y, c.z, c.t};
+  const size_t pbase = (size_t)par * nblk * per << sbl;
+  auto lex = [&](const int* q) { return q[0] + g.L[0] * (q[1] + g.L[1] * (q[2] + g.L[2] * q[3])); };
+  const int idx = lex(co);
+  for (int mu = 0; mu < 4; ++mu) {
+    int esum = 0;
+    for (int nu = 0; nu < mu; ++nu) esum += co[nu];
+    const double eta = (esum & 1) ? -0.5 : 0.5;
+    for (int h = 0; h < 2; ++h) {  // h = 0: one-hop V, h = 1: three-hop W
+      const int dist = h ? 3 : 1;
+      const double2* F = h ? W : V;
+      const double ff = eta * ((co[mu] + dist >= g.L[mu]) ? bc.b[mu] : 1);
+      const double2* uf = F + ((size_t)mu * vol + idx) * 9;
+      for (int e = 0; e < 9; ++e) {
+        double2 v = cscale(uf[e], ff);
+        size_t o = pbase + link_off(s, 8 * h + mu, e, sbl, per);
+        l64[o] = v;
+        l32[o] = make_float2((float)v.x, (float)v.y);
+      }
+      int nb[4] = {co[0], co[1], co[2], co[3]};
+      nb[mu] = co[mu] - dist < 0 ? co[mu] - dist + g.L[mu] : co[mu] - dist;
+      const double fb = -eta * ((co[mu] - dist < 0) ? bc.b[mu] : 1);
+      const double2* ub = F + ((size_t)mu * vol + lex(nb)) * 9;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double2 v = cscale(cconj(ub[3 * b + a]), fb);
+          size_t o = pbase + link_off(s, 8 * h + 4 + mu, 3 * a + b, sbl, per);
+          l64[o] = v;
+          l32[o] = make_float2((float)v.x, (float)v.y);
+        }
+    }
+  }
+}
+
 // A link element, loaded with the non-temporal hint when NT (the links are
 // read once per half hop; the hint keeps them from displacing the input
 // block's neighbour columns in L2).
@@ -115,7 +172,7 @@ __device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom
 // neighbouring columns) and a wave touches as few cache lines as the bytes
 // allow. In FP32 a thread's R columns are consecutive instead (g*R .. g*R+R-1),
 // which the compiler loads as 16-byte vectors.
-template <typename T, int R, bool NT>
+template <typename T, int R, bool NT, int NL>
 __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ links,
                                                 const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out,
@@ -148,11 +205,11 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
     for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
   const size_t st = (size_t)1 << sbl;
 #pragma unroll 2
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < NL; ++k) {
     int mu = k & 3;
-    int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
+    int nb = neighbour_cb((int)s, c, g, mu, hop_dist(k));
     const C* src = in + (size_t)nb * 3 * n + j0;
-    const C* L = links + link_off(s, k, 0, sbl);
+    const C* L = links + link_off(s, k, 0, sbl, 9 * NL);
     C l[9], v[3][R];
 #pragma unroll
     for (int e = 0; e < 9; ++e) l[e] = link_ld<NT>(L + e * st);
@@ -200,7 +257,7 @@ __device__ __forceinline__ double quad_bcast(double v) {
 // element e reaches the other three threads of the quad by a DPP broadcast
 // from lane e % 4. Columns as in k_hop (interleaved in FP64, consecutive in
 // FP32).
-template <typename T, int R, bool NT>
+template <typename T, int R, bool NT, int NL>
 __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ links,
                                                   const cplx<T>* __restrict__ in,
                                                   cplx<T>* __restrict__ out,
@@ -229,11 +286,11 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
   // before any of them is used; the scheduling barrier keeps the scheduler
   // from spreading them next to their uses, which leaves about two in flight.
 #pragma unroll 2
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < NL; ++k) {
     const int mu = k & 3;
-    const int nb = neighbour_cb((int)s, c, g, mu, k < 4 ? 1 : -1);
+    const int nb = neighbour_cb((int)s, c, g, mu, hop_dist(k));
     const C* src = in + (size_t)nb * 3 * n + j0;
-    const C* L = links + link_off(s, k, 0, sbl);
+    const C* L = links + link_off(s, k, 0, sbl, 9 * NL);
     const C t0 = link_ld<NT>(L + q * st), t1 = link_ld<NT>(L + (q + 4) * st),
             t2 = link_ld<NT>(L + e2 * st);
     C v[3][R];
@@ -278,6 +335,17 @@ hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void*
   uint32_t nthr = 2u * c->vh;
   k_gauge_import<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(
       (const double2*)U, (double2*)l64, (float2*)l32, c->geom, bc, c->sbl, c->nblk, (int)c->vol);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge_import_improved(const bms_ctx* c, const void* V, const void* W, void* l64,
+                                        void* l32) {
+  Bc bc;
+  for (int i = 0; i < 4; ++i) bc.b[i] = c->bc[i];
+  uint32_t nthr = 2u * c->vh;
+  k_gauge_import_improved<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(
+      (const double2*)V, (const double2*)W, (double2*)l64, (float2*)l32, c->geom, bc, c->sbl,
+      c->nblk, (int)c->vol);
   return hipGetLastError();
 }
 
@@ -344,7 +412,7 @@ template <typename T>
 hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
                       double a, double b, const int* skip) {
   const DevBuf& lb = sizeof(T) == 8 ? c->links64 : c->links32;
-  size_t pstride = (size_t)c->nblk * 72 << c->sbl;
+  size_t pstride = (size_t)c->nblk * 9 * c->nlinks << c->sbl;
   const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
   // Variants: 0 one thread per (site, column group), 1 four threads per site
   // sharing the links (n = 4, 8, 16, 32), 2 and 3 the same in the tiled
@@ -356,15 +424,20 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   if (hp.quad) {
     dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);
     HopTiles tiles = hp.tiled ? hop_tiles(c, BMS_WG / 4, hp.ty, hp.tz, hp.tt) : HopTiles{};
-#define HOPQ(RR, NT)                                                                       \
-  k_hop_q<T, RR, NT><<<qgrid, BMS_WG, lds, c->stream>>>(                                   \
+#define HOPQ(RR, NT, NL)                                                                   \
+  k_hop_q<T, RR, NT, NL><<<qgrid, BMS_WG, lds, c->stream>>>(                               \
       links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom,  \
       n, par, c->sbl, skip, tiles)
-#define HOPQN(RR) \
-  if (hp.nt)      \
-    HOPQ(RR, true); \
-  else            \
-    HOPQ(RR, false)
+#define HOPQN(RR)                                   \
+  if (c->nlinks == 16) {                            \
+    if (hp.nt)                                      \
+      HOPQ(RR, true, 16);                           \
+    else                                            \
+      HOPQ(RR, false, 16);                          \
+  } else if (hp.nt)                                 \
+    HOPQ(RR, true, 8);                              \
+  else                                              \
+    HOPQ(RR, false, 8)
     switch (n) {
       case 4: HOPQN(1); break;
       case 8: HOPQN(2); break;
@@ -383,16 +456,20 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   HopTiles tiles = hp.tiled && BMS_WG % ngrp == 0
                        ? hop_tiles(c, BMS_WG / (int)ngrp, hp.ty, hp.tz, hp.tt)
                        : HopTiles{};
-#define HOP_LAUNCH(RR, NT)                                                                 \
-  k_hop<T, RR, NT><<<grid, BMS_WG, lds, c->stream>>>(links, (const cplx<T>*)in,            \
-                                                  (cplx<T>*)out, (const cplx<T>*)aux, (T)a, \
-                                                  (T)b, c->geom, n, dg, par, c->sbl, skip, \
-                                                  tiles)
-#define HOPN(RR)        \
-  if (hp.nt)            \
-    HOP_LAUNCH(RR, true); \
-  else                  \
-    HOP_LAUNCH(RR, false)
+#define HOP_LAUNCH(RR, NT, NL)                                                             \
+  k_hop<T, RR, NT, NL><<<grid, BMS_WG, lds, c->stream>>>(                                  \
+      links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom,  \
+      n, dg, par, c->sbl, skip, tiles)
+#define HOPN(RR)                                    \
+  if (c->nlinks == 16) {                            \
+    if (hp.nt)                                      \
+      HOP_LAUNCH(RR, true, 16);                     \
+    else                                            \
+      HOP_LAUNCH(RR, false, 16);                    \
+  } else if (hp.nt)                                 \
+    HOP_LAUNCH(RR, true, 8);                        \
+  else                                              \
+    HOP_LAUNCH(RR, false, 8)
   if (R == 4)
     HOPN(4);
   else if (R == 2)

@@ -105,6 +105,7 @@ struct bms_ctx {
   int lds_per_cu = 0;  // bytes of LDS per compute unit (set with the stream)
   int lds_per_block = 0;  // bytes of LDS one work-group may take
   bool gauge_set = false;
+  int nlinks = 8;  // links per site and output parity: 8, or 16 with three-hop links
   DevBuf links64, links32;  // [parity][blocked links] complex
   std::vector<DevBuf> scratch;  // named by slot index
   std::string last_error;
@@ -153,6 +154,9 @@ int stream_end(bms_ctx* c);
 
 // ---- launchers (all enqueue on c->stream) ---------------------------------
 hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32);
+// the improved operator: one-hop links V and three-hop links W (16 per site)
+hipError_t launch_gauge_import_improved(const bms_ctx* c, const void* V, const void* W, void* l64,
+                                        void* l32);
 
 // out = b * D_{par} in  (+ a * aux if aux)  on n columns; done = optional
 // device flag (skip if *done)

@@ -243,7 +243,7 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
   struct {
     const void* p[16];
     double mass;
-    int K, n, ns, nb, hop_v, gram_v, upd_v, prec;
+    int K, n, ns, nb, hop_v, gram_v, upd_v, prec, nlinks;
     HopCfg hop_cfg[2];
     SmallParams sp;
     SmallState sm;
@@ -261,6 +261,7 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
   k.gram_v = c->gram_variant;
   k.upd_v = c->update_variant;
   k.prec = (int)sizeof(T);
+  k.nlinks = c->nlinks;
   k.hop_cfg[0] = c->hop_cfg[0];
   k.hop_cfg[1] = c->hop_cfg[1];
   k.sp = sp;
@@ -365,7 +366,7 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
     HIP_TRY(c, hipMemcpyAsync(&hf, w.flags, sizeof hf, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->timing) {
-      double G = 72.0 * c->vol * sizeof(T);
+      double G = 9.0 * c->nlinks * c->vol * sizeof(T);
       double S = (double)w.blk * sizeof(cplx<T>);
       // the explicit Cholesky-QR Gram (slot 4) normally exits at once: no bytes
       const double kbytes[7] = {G + 2 * S, G + 3 * S, 3 * S, 0, 0, 0, 0};
