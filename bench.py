@@ -265,6 +265,34 @@ def operator_block_gain(bms, torch, dims, Ud, reps=5):
     return out
 
 
+def rhmc_measure(bms, torch, np, configs):
+    """One RHMC trajectory at the paper's settings (force solves at 1e-7,
+    heatbath and action at 1e-14, two-level Omelyan with lambda = 1/6, three
+    gauge steps per fermion step, tau = 1) on the 8^4 workload (n_pf = 4,
+    m = 0.05, beta = 5.12): wall time, dH and the solver work."""
+    from paper_1808_01829_amd.inputs import gaussian_block, random_gauge
+    w = configs.WORKLOADS["c2"]
+    dims, n = w["dims"], w["n"]
+    c = bms.Context(dims, (1, 1, 1, -1))
+    U = torch.from_numpy(random_gauge(dims, 0.3, 9001)).cuda()
+    P = torch.from_numpy(np.random.default_rng(9002).standard_normal(
+        (4, int(np.prod(dims)), 8))).cuda()
+    eta = torch.from_numpy(gaussian_block(dims, n, 9003)).cuda()
+    kw = dict(r_hb=configs.heatbath_coefficients("c2"), r_acc=configs.accept_coefficients("c2"),
+              r_md=configs.workload_coefficients("c2"), tau=1.0, n_steps=10, n_gauge=3)
+    bms.rhmc_trajectory(c, U.clone(), P.clone(), eta, 5.12, w["mass"], **kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = bms.rhmc_trajectory(c, U, P, eta, 5.12, w["mass"], **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(workload="c2: 8x8x8x8, n_pf=4, m=0.05, beta=5.12, tau=1, 10 steps x 3 gauge "
+                         "steps, OMF2 lambda=1/6", s_per_trajectory=round(dt, 3),
+                dH=res["dH"], acceptance=round(min(1.0, float(np.exp(-res["dH"]))), 4),
+                force_evals=res["force_evals"], block_iterations=res["iterations"],
+                heatbath_action_residual=res["max_residual_hb"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +315,8 @@ def main():
                          "(median, min, max reported aside)")
     ap.add_argument("--no-force", action="store_true",
                     help="skip the force-kernel measurement (reported aside)")
+    ap.add_argument("--no-rhmc", action="store_true",
+                    help="skip the RHMC trajectory measurement (reported aside)")
     ap.add_argument("--no-operators", action="store_true",
                     help="skip the unimproved/improved operator comparison (reported aside)")
     args = ap.parse_args()
@@ -446,6 +476,11 @@ def main():
         operators = operator_block_gain(bms, torch, dims, Ud)
         log("bench: operators %s" % (operators,))
 
+    rhmc = None
+    if not args.no_rhmc:
+        rhmc = rhmc_measure(bms, torch, np, configs)
+        log("bench: rhmc %s" % (rhmc,))
+
     force = None
     if not args.no_force:
         force = force_measure(bms, torch, np, configs)
@@ -490,6 +525,7 @@ def main():
         action=action,
         force=force,
         operators=operators,
+        rhmc=rhmc,
         per_vector=dict(value=round(pv_rate, 4) if pv_rate == pv_rate else None,
                         unit="RHS-solves/s", columns=args.baseline_cols,
                         iterations=pv_iters, dtype="f64"),

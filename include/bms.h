@@ -241,6 +241,8 @@ int bms_action_noalloc(bms_ctx* ctx, int n, int n_shifts, double a0, const doubl
 #define BMS_FORCE_RAW 0 /* G = dS/dRe U + i dS/dIm U, [mu][idx][3][3] complex128 */
 #define BMS_FORCE_LIE 1 /* F^a = -dS/d omega^a for U -> exp(i omega^a T^a) U, T^a = lambda_a/2,
                            [mu][idx][8] float64 */
+#define BMS_FORCE_ADD 2 /* or-ed into flags: out += the result instead of out = (e.g. a
+                           momentum update P += eps F with alpha scaled by eps) */
 
 /*
  * Link derivative of S = sum_i sum_j alpha[j] phi_i^dag (A + s_j)^-1 phi_i
@@ -250,10 +252,89 @@ int bms_action_noalloc(bms_ctx* ctx, int n, int n_shifts, double a0, const doubl
  * i.e. per link M_mu(w) = -eta b sum alpha x(w+mu) y(w)^dag (w odd) or
  * +eta b sum alpha y(w+mu) x(w)^dag (w even), returned as G = M^dag
  * (flags = BMS_FORCE_RAW) or F^a = Im Tr[T^a U M] (BMS_FORCE_LIE).
- * out is a device array overwritten in full.
+ * out is a device array overwritten in full, or added to with BMS_FORCE_ADD.
+ * Defined for the unimproved operator (BMS_EINVAL after bms_set_gauge_improved).
  */
 int bms_force(bms_ctx* ctx, int n, int n_shifts, const double* alpha, const void* X, void* out,
               int flags);
+
+/*
+ * Gauge-field steps of an RHMC trajectory (the Wilson gauge part of the HMC
+ * Hamiltonian, Sec. II and Sec. IV), on the context's lattice. Links U
+ * [mu][idx][3][3] complex128 (periodic), momenta P [mu][idx][8] float64
+ * (components along T^a = lambda_a / 2), all device pointers.
+ *   bms_gauge_action    S = beta sum_{x, mu<nu} (1 - Re Tr U_mu nu(x) / 3) (host double)
+ *   bms_gauge_force     P += scale F, F^a = -dS/d omega^a for U -> exp(i omega^a T^a) U,
+ *                       i.e. F^a = -(beta/3) Im Tr(T^a U_mu(x) A_mu(x)) with the
+ *                       staple sum A of the six plaquettes through the link
+ *   bms_gauge_update    U <- exp(i eps P^a T^a) U (every link)
+ *   bms_kinetic_energy  K = 1/2 sum (P^a)^2 (host double)
+ * The sums block until done. Errors: BMS_EINVAL for NULL or non-finite arguments.
+ */
+int bms_gauge_action(bms_ctx* ctx, double beta, const void* U, double* S);
+int bms_gauge_force(bms_ctx* ctx, double beta, const void* U, void* P, double scale);
+int bms_gauge_update(bms_ctx* ctx, double eps, const void* P, void* U);
+int bms_kinetic_energy(bms_ctx* ctx, const void* P, double* K);
+
+/* Parameters of bms_rhmc_trajectory; bms_default_rhmc_params fills the
+   defaults shown (and NULL coefficient pointers). */
+typedef struct bms_rhmc_params {
+  double beta;       /* Wilson gauge coupling (5.12) */
+  double mass;       /* staggered mass m (0.05) */
+  int n;             /* pseudofermions = block width (1); 0 runs pure gauge HMC */
+  double tau;        /* trajectory length (1) */
+  int n_steps;       /* outer Omelyan steps, fermion force (10) */
+  int n_gauge;       /* inner Omelyan steps of the gauge force per outer drift (3) */
+  double lambda;     /* Omelyan parameter (1/6) */
+  int ns_hb;         /* heatbath r_hb(x) ~ x^(+p/2): a0 + sum alpha/(x + beta) */
+  double a0_hb;
+  const double* alpha_hb;
+  const double* beta_hb;
+  int ns_acc;        /* action r(x) ~ x^(-p) for H (heatbath and accept accuracy) */
+  double a0_acc;
+  const double* alpha_acc;
+  const double* beta_acc;
+  int ns_md;         /* force r(x) ~ x^(-p) (molecular-dynamics accuracy; a0 drops out) */
+  const double* alpha_md;
+  const double* beta_md;
+  double tol_hb;     /* heatbath and action solves (1e-14) */
+  double tol_md;     /* force solves (1e-7) */
+  int precision_md;  /* BMS_PREC_F64 (default) or BMS_PREC_MIXED for the force solves */
+  int max_iter;      /* block iterations per solve (100000) */
+} bms_rhmc_params;
+
+typedef struct bms_rhmc_result {
+  double H0, H1, dH;        /* H = K + S_g + S_f before and after the molecular dynamics */
+  double K0, K1, Sg0, Sg1, Sf0, Sf1;
+  double max_residual_hb;   /* worst true residual of the heatbath and action solves */
+  long long iterations;     /* block iterations of every solve */
+  int force_evals;          /* fermion-force evaluations */
+} bms_rhmc_result;
+
+void bms_default_rhmc_params(bms_rhmc_params* p);
+
+/*
+ * One RHMC trajectory (Sec. II; the settings of Sec. IV) with n pseudofermions
+ * solved as one block:
+ *   heatbath phi = r_hb(A) eta (bms_rational_apply at tol_hb);
+ *   H0 = 1/2 sum P^2 + S_g(U) + sum_i phi_i^dag r(A) phi_i (accept rational, tol_hb);
+ *   molecular dynamics over tau by the two-level second-order Omelyan scheme:
+ *   with h = tau / n_steps, per step P += lambda h F_f, a link drift over h/2,
+ *   P += (1 - 2 lambda) h F_f, a drift over h/2, P += lambda h F_f (the kicks of
+ *   adjacent steps merged), each drift being n_gauge Omelyan steps of the
+ *   gauge force and U <- exp(i e P) U; the fermion force F_f is bms_force's Lie
+ *   force of the force rational with its solves at tol_md;
+ *   H1 and dH = H1 - H0.
+ * U (in/out) and P (in/out, momenta drawn by the caller as P^a ~ N(0, 1)) are
+ * device arrays in the layouts above; eta is the device Gaussian block
+ * [cb][color][n] complex128 (NULL when n = 0). The caller keeps a copy of U
+ * and accepts with probability min(1, exp(-dH)). The library's own copy of
+ * the links follows U (bms_set_gauge is called on every new U).
+ * Errors: BMS_EINVAL for bad parameters; a failing solve's status (r holds
+ * what was computed up to it); BMS_ENAN for a non-finite energy.
+ */
+int bms_rhmc_trajectory(bms_ctx* ctx, const bms_rhmc_params* p, void* U, void* P,
+                        const void* eta, bms_rhmc_result* r);
 
 /*
  * Per-kernel GPU timing. While enabled, bms_solve records HIP events on the

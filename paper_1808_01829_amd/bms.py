@@ -45,7 +45,9 @@ EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create
            "bms_force", "bms_timing_enable", "bms_timing_read", "bms_set_variant",
            "bms_get_variant", "bms_autotune", "bms_solve_batch", "bms_action_noalloc",
            "bms_rational_apply", "bms_set_hop_config", "bms_get_hop_config",
-           "bms_set_tune_cache", "bms_set_gauge_improved"]
+           "bms_set_tune_cache", "bms_set_gauge_improved", "bms_gauge_action",
+           "bms_gauge_force", "bms_gauge_update", "bms_kinetic_energy",
+           "bms_default_rhmc_params", "bms_rhmc_trajectory"]
 
 
 class bms_opts(ctypes.Structure):
@@ -75,6 +77,28 @@ def _stats_dict(st):
     return d
 
 
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class bms_rhmc_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mass", ctypes.c_double), ("n", ctypes.c_int),
+                ("tau", ctypes.c_double), ("n_steps", ctypes.c_int), ("n_gauge", ctypes.c_int),
+                ("lambda_", ctypes.c_double),
+                ("ns_hb", ctypes.c_int), ("a0_hb", ctypes.c_double), ("alpha_hb", _dp),
+                ("beta_hb", _dp),
+                ("ns_acc", ctypes.c_int), ("a0_acc", ctypes.c_double), ("alpha_acc", _dp),
+                ("beta_acc", _dp),
+                ("ns_md", ctypes.c_int), ("alpha_md", _dp), ("beta_md", _dp),
+                ("tol_hb", ctypes.c_double), ("tol_md", ctypes.c_double),
+                ("precision_md", ctypes.c_int), ("max_iter", ctypes.c_int)]
+
+
+class bms_rhmc_result(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("H0", "H1", "dH", "K0", "K1", "Sg0", "Sg1", "Sf0",
+                                                "Sf1", "max_residual_hb")] + \
+               [("iterations", ctypes.c_longlong), ("force_evals", ctypes.c_int)]
+
+
 class BmsError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (_lib().bms_error_string(code).decode(), msg))
@@ -102,6 +126,14 @@ def _lib():
         L.bms_destroy.argtypes = [vp]
         L.bms_set_gauge.argtypes = [vp, vp]
         L.bms_set_gauge_improved.argtypes = [vp, vp, vp]
+        L.bms_gauge_action.argtypes = [vp, d, vp, dp]
+        L.bms_gauge_force.argtypes = [vp, d, vp, vp, d]
+        L.bms_gauge_update.argtypes = [vp, d, vp, vp]
+        L.bms_kinetic_energy.argtypes = [vp, vp, dp]
+        L.bms_default_rhmc_params.argtypes = [ctypes.POINTER(bms_rhmc_params)]
+        L.bms_default_rhmc_params.restype = None
+        L.bms_rhmc_trajectory.argtypes = [vp, ctypes.POINTER(bms_rhmc_params), vp, vp, vp,
+                                          ctypes.POINTER(bms_rhmc_result)]
         L.bms_apply_hop.argtypes = [vp, i, i, vp, vp, i]
         L.bms_apply_mdagm.argtypes = [vp, d, d, i, vp, vp, i]
         L.bms_solve.argtypes = [vp, d, i, i, dp, d, i, ctypes.POINTER(bms_opts), vp, vp,
@@ -124,7 +156,8 @@ def _lib():
                                       ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(bms_stats), ip]
         for f in EXPORTS:
-            if f not in ("bms_default_opts", "bms_error_string", "bms_last_error"):
+            if f not in ("bms_default_opts", "bms_error_string", "bms_last_error",
+                         "bms_default_rhmc_params"):
                 getattr(L, f).restype = ctypes.c_int
         _L = L
     return _L
@@ -370,6 +403,24 @@ class Context:
         assert U.dtype == torch.complex128 and tuple(U.shape) == (4, self.vol, 3, 3)
         bms_set_gauge(self.h, U)
 
+    def gauge_action(self, beta, U):
+        S = ctypes.c_double()
+        _check(self.h, _lib().bms_gauge_action(self.h, float(beta), _ptr(U), ctypes.byref(S)))
+        return S.value
+
+    def gauge_force(self, beta, U, P, scale=1.0):
+        """P += scale * F (Wilson gauge force, su(3) components)."""
+        _check(self.h, _lib().bms_gauge_force(self.h, float(beta), _ptr(U), _ptr(P), float(scale)))
+
+    def gauge_update(self, eps, P, U):
+        """U <- exp(i eps P^a T^a) U in place."""
+        _check(self.h, _lib().bms_gauge_update(self.h, float(eps), _ptr(P), _ptr(U)))
+
+    def kinetic_energy(self, P):
+        K = ctypes.c_double()
+        _check(self.h, _lib().bms_kinetic_energy(self.h, _ptr(P), ctypes.byref(K)))
+        return K.value
+
     def set_gauge_improved(self, V, W):
         """One-hop links V and three-hop links W of the improved operator
         (coefficients folded in), both shaped like U."""
@@ -475,6 +526,39 @@ class Context:
             out = torch.empty((4, self.vol, 8), dtype=torch.float64, device=X.device)
         bms_force(self.h, n, list(alpha), X, out, flags)
         return out
+
+
+def rhmc_trajectory(ctx, U, P, eta, beta, mass, r_hb=None, r_acc=None, r_md=None, tau=1.0,
+                    n_steps=10, n_gauge=3, lam=1.0 / 6.0, tol_hb=1e-14, tol_md=1e-7,
+                    precision_md=BMS_PREC_F64, max_iter=100000):
+    """bms_rhmc_trajectory on a Context: U (links, in/out) and P (momenta,
+    in/out) device tensors, eta the Gaussian block (None for pure gauge HMC);
+    r_* the heatbath, action and force rational approximations. Returns the
+    result as a dict."""
+    p = bms_rhmc_params()
+    _lib().bms_default_rhmc_params(ctypes.byref(p))
+    p.beta, p.mass, p.tau = float(beta), float(mass), float(tau)
+    p.n_steps, p.n_gauge, p.lambda_ = int(n_steps), int(n_gauge), float(lam)
+    p.tol_hb, p.tol_md, p.precision_md, p.max_iter = float(tol_hb), float(tol_md), \
+        int(precision_md), int(max_iter)
+    keep = []
+    if eta is None:
+        p.n = 0
+    else:
+        p.n = int(eta.shape[2])
+        for tag, r in (("hb", r_hb), ("acc", r_acc), ("md", r_md)):
+            al, be = _doubles(r.alpha), _doubles(r.beta)
+            keep += [al, be]
+            setattr(p, "ns_" + tag, len(r.beta))
+            setattr(p, "alpha_" + tag, ctypes.cast(al, _dp))
+            setattr(p, "beta_" + tag, ctypes.cast(be, _dp))
+            if tag != "md":
+                setattr(p, "a0_" + tag, float(r.a0))
+    res = bms_rhmc_result()
+    rc = _lib().bms_rhmc_trajectory(ctx.h, ctypes.byref(p), _ptr(U), _ptr(P),
+                                    _ptr(eta) if eta is not None else None, ctypes.byref(res))
+    _check(ctx.h, rc)
+    return {k: getattr(res, k) for k, _ in bms_rhmc_result._fields_}
 
 
 def solve_batch(contexts, masses, shifts, Bs, tol=1e-10, max_iter=10000, opts=None,

@@ -18,7 +18,7 @@ namespace {
 struct ForceArgs {
   Geom g;
   int bc[4];
-  int n, ns, sbl, lie;
+  int n, ns, sbl, lie, add;
   const double2* X;      // [ns][vh][3][n] even sites
   const double2* Y;      // [ns][vh][3][n] odd sites, Y = D_oe X
   const double2* links;  // FP64 internal links, both parities
@@ -113,7 +113,10 @@ __global__ __launch_bounds__(BMS_WG) void k_force(ForceArgs a, int lpl) {
     double2* G = a.G + lo * 9;
 #pragma unroll
     for (int e = 0; e < 9; ++e)
-      if (e % lpl == lane) G[e] = cconj(m[3 * (e % 3) + e / 3]);
+      if (e % lpl == lane) {
+        const double2 v = cconj(m[3 * (e % 3) + e / 3]);
+        G[e] = a.add ? cadd(G[e], v) : v;
+      }
     return;
   }
   if (lane != 0) return;
@@ -131,15 +134,17 @@ __global__ __launch_bounds__(BMS_WG) void k_force(ForceArgs a, int lpl) {
       w[3 * i + j] = s;
     }
   // Tr[T W] = sum_ij T_ij W_ji
+  double fv[8];
+  fv[0] = 0.5 * (w[3].y + w[1].y);                   // lambda_1: (0,1),(1,0)
+  fv[1] = 0.5 * (-(w[3].x) + w[1].x);                // lambda_2: -i at (0,1), +i at (1,0)
+  fv[2] = 0.5 * (w[0].y - w[4].y);                   // lambda_3
+  fv[3] = 0.5 * (w[6].y + w[2].y);                   // lambda_4: (0,2),(2,0)
+  fv[4] = 0.5 * (-(w[6].x) + w[2].x);                // lambda_5
+  fv[5] = 0.5 * (w[7].y + w[5].y);                   // lambda_6: (1,2),(2,1)
+  fv[6] = 0.5 * (-(w[7].x) + w[5].x);                // lambda_7
+  fv[7] = 0.5 / sqrt(3.0) * (w[0].y + w[4].y - 2.0 * w[8].y);  // lambda_8
   double* F = a.F + lo * 8;
-  F[0] = 0.5 * (w[3].y + w[1].y);                   // lambda_1: (0,1),(1,0)
-  F[1] = 0.5 * (-(w[3].x) + w[1].x);                // lambda_2: -i at (0,1), +i at (1,0)
-  F[2] = 0.5 * (w[0].y - w[4].y);                   // lambda_3
-  F[3] = 0.5 * (w[6].y + w[2].y);                   // lambda_4: (0,2),(2,0)
-  F[4] = 0.5 * (-(w[6].x) + w[2].x);                // lambda_5
-  F[5] = 0.5 * (w[7].y + w[5].y);                   // lambda_6: (1,2),(2,1)
-  F[6] = 0.5 * (-(w[7].x) + w[5].x);                // lambda_7
-  F[7] = 0.5 / sqrt(3.0) * (w[0].y + w[4].y - 2.0 * w[8].y);  // lambda_8
+  for (int k = 0; k < 8; ++k) F[k] = a.add ? F[k] + fv[k] : fv[k];
 }
 
 // Quad sum by DPP: every lane of each group of four ends with the group's sum.
@@ -327,7 +332,10 @@ __global__ __launch_bounds__(BMS_WG, WAVES) void k_force_fused(ForceArgs a) {
     double2* G = a.G + lo * 9;
 #pragma unroll
     for (int e = 0; e < 9; ++e)
-      if ((e & 1) == (gl & 1)) G[e] = cconj(m[3 * (e % 3) + e / 3]);
+      if ((e & 1) == (gl & 1)) {
+        const double2 v = cconj(m[3 * (e % 3) + e / 3]);
+        G[e] = a.add ? cadd(G[e], v) : v;
+      }
     return;
   }
   if (gl & 1) return;
@@ -355,15 +363,18 @@ __global__ __launch_bounds__(BMS_WG, WAVES) void k_force_fused(ForceArgs a) {
       for (int k = 0; k < 3; ++k) t = cfma(u[3 * r + k], m[3 * k + b], t);
       w[3 * r + b] = t;
     }
+  double f[8];
+  f[0] = 0.5 * (w[3].y + w[1].y);
+  f[1] = 0.5 * (-(w[3].x) + w[1].x);
+  f[2] = 0.5 * (w[0].y - w[4].y);
+  f[3] = 0.5 * (w[6].y + w[2].y);
+  f[4] = 0.5 * (-(w[6].x) + w[2].x);
+  f[5] = 0.5 * (w[7].y + w[5].y);
+  f[6] = 0.5 * (-(w[7].x) + w[5].x);
+  f[7] = 0.5 / sqrt(3.0) * (w[0].y + w[4].y - 2.0 * w[8].y);
   double* F = a.F + lo * 8;
-  F[0] = 0.5 * (w[3].y + w[1].y);
-  F[1] = 0.5 * (-(w[3].x) + w[1].x);
-  F[2] = 0.5 * (w[0].y - w[4].y);
-  F[3] = 0.5 * (w[6].y + w[2].y);
-  F[4] = 0.5 * (-(w[6].x) + w[2].x);
-  F[5] = 0.5 * (w[7].y + w[5].y);
-  F[6] = 0.5 * (-(w[7].x) + w[5].x);
-  F[7] = 0.5 / sqrt(3.0) * (w[0].y + w[4].y - 2.0 * w[8].y);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) F[k] = a.add ? F[k] + f[k] : f[k];
 }
 
 }  // namespace
@@ -374,7 +385,7 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   if (n < 1 || n > BMS_MAX_RHS) return set_err(c, BMS_EINVAL, "n must be in [1, %d]", BMS_MAX_RHS);
   if (ns < 1 || ns > BMS_MAX_SHIFTS) return set_err(c, BMS_EINVAL, "bad n_shifts");
   if (!alpha || !X || !out) return set_err(c, BMS_EINVAL, "null pointer");
-  if (flags != BMS_FORCE_RAW && flags != BMS_FORCE_LIE) return set_err(c, BMS_EINVAL, "bad flags");
+  if (flags < 0 || flags > (BMS_FORCE_LIE | BMS_FORCE_ADD)) return set_err(c, BMS_EINVAL, "bad flags");
   for (int s = 0; s < ns; ++s)
     if (!std::isfinite(alpha[s])) return set_err(c, BMS_EINVAL, "alpha[%d] not finite", s);
   if (!c->gauge_set) return set_err(c, BMS_ESTATE, "no gauge field set");
@@ -393,7 +404,8 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
   a.n = n;
   a.ns = ns;
   a.sbl = c->sbl;
-  a.lie = flags == BMS_FORCE_LIE;
+  a.lie = (flags & BMS_FORCE_LIE) != 0;
+  a.add = (flags & BMS_FORCE_ADD) != 0;
   a.X = (const double2*)X;
   a.Y = (const double2*)Y;
   a.links = (const double2*)c->links64.p;
@@ -442,8 +454,8 @@ extern "C" int bms_force(bms_ctx* c, int n, int ns, const double* alpha, const v
     c->kt_launches[BMS_KERNEL_FORCE] += 1;
     c->kt_bytes[BMS_KERNEL_FORCE] += (double)ns * blk * sizeof(double2) + 4 * vol * 9 * 16 +
                                      (a.lie ? 4 * vol * 8 * 8 : 4 * vol * 9 * 16);
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
   }
   return stream_end(c);
 }

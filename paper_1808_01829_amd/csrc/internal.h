@@ -38,6 +38,8 @@ enum Slot {
   S_E2,       // FP64 solutions of the FP32 multi-shift phase
   S_CMAT,     // n x n FP64 coefficient matrix
   S_Y,        // bms_force: Y = D_oe X of every shift (odd sites)
+  S_PHI,      // RHMC trajectory: the pseudofermion block phi
+  S_XR,       // RHMC trajectory: shifted solutions of phi
   S_COUNT
 };
 
@@ -151,6 +153,12 @@ int solve_validate(bms_ctx* c, double mass, int n, int ns, const double* shifts,
 int solve_reserve(bms_ctx* c, double mass, int n, int ns, const double* shifts, double tol,
                   int max_iter, const bms_opts* opts, const void* B, const void* X);
 int stream_end(bms_ctx* c);
+
+// gauge-field steps of the RHMC trajectory (gauge.hip), on c->stream
+int gauge_action_dev(bms_ctx* c, double beta, const void* U, double* S);
+int gauge_force_dev(bms_ctx* c, double beta, const void* U, void* P, double scale);
+int link_update_dev(bms_ctx* c, double eps, const void* P, void* U);
+int kinetic_dev(bms_ctx* c, const void* P, double* K);
 
 // ---- launchers (all enqueue on c->stream) ---------------------------------
 hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32);
