@@ -234,6 +234,8 @@ struct CoreResult {
   int soft = 0;   // the iteration stopped early on breakdown / non-finite values
   int reliable = 0;
   bool diverged = false;  // the mixed iteration's true residual grew (stopped softly)
+  bool exhausted = false; // FP32 loop stopped at twice the block Krylov dimension
+  bool extended = false;  // the FP64 phase went on to the final tolerance
 };
 
 // Everything the kernels of one iteration receive by value or address: a
@@ -318,7 +320,7 @@ int enqueue_chunk(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
 template <typename T>
 int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, const int* xmap,
                double tol, int max_iter, const bms_opts& o, const void* B, void* Xout,
-               CoreResult& cr) {
+               CoreResult& cr, double extend_tol = 0.0) {
   int rc;
   const bool mixed = sizeof(T) == 4;
   SmallParams sp;
@@ -326,6 +328,15 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
   sp.n = n;
   sp.ns = ns;
   sp.max_iter = max_iter;
+  // In exact arithmetic block CG ends within ceil(rows / n) iterations (the
+  // block Krylov space is then the whole space). An FP32 loop still running
+  // at twice that has lost the recurrence to rounding and creeps along (seen
+  // on 8^4 with n = 16 at m = 0.01: 42 000 FP32 iterations against 538 in
+  // FP64), so it stops there and the caller finishes in FP64 (the FP32-only
+  // solve through its full FP64 restart, the two-phase solve by redoing the
+  // correction solve in FP64).
+  const long kdim = (3L * c->vh + n - 1) / n;
+  if (mixed && 2 * kdim < max_iter) sp.max_iter = (int)(2 * kdim);
   // The recurrence's residual estimate drifts from the true residual by
   // rounding; stopping (and freezing) at tol/2 leaves that margin.
   sp.tol = 0.5 * tol;
@@ -384,6 +395,16 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
     }
     enqueued += K;
     if (hf.stop) break;
+    // extend_tol > 0 (the FP64 phase of the mixed solver): once the block
+    // Krylov space is half spanned the residual block sits in the few modes
+    // left, its columns nearly dependent, and the last iterations converge
+    // fast; an FP32 phase started from it would have to rebuild that space
+    // (and its Cholesky-QR loses rank), so this solve goes on to extend_tol.
+    if (extend_tol > 0 && !cr.extended && 2L * hf.iter >= kdim) {
+      sp.tol = 0.5 * extend_tol;
+      sp.freeze_tol = std::min(sp.freeze_tol, sp.tol);
+      cr.extended = true;
+    }
     if (enqueued > (long)max_iter + 2L * K)  // the device stops itself at max_iter
       return set_err(c, BMS_EHIP, "device iteration control did not stop (iter %d)", hf.iter);
   }
@@ -409,6 +430,12 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
   cr.iters = hf.iter;
   cr.reliable = hf.rel_count;
   cr.diverged = hf.diverged != 0;
+  bool all_conv = true;
+  for (int s = 0; s < ns; ++s) all_conv = all_conv && hf.conv[s];
+  if (sp.max_iter < max_iter && hf.iter >= sp.max_iter && !all_conv) {
+    cr.exhausted = true;
+    cr.diverged = true;  // no usable FP32 result: the caller goes on in FP64
+  }
   (mixed ? c->it_f32 : c->it_f64) += hf.iter;
   c->hop_work += 2L * hf.iter + 2L * hf.rel_count;
   // A breakdown or non-finite value inside the iteration stops it with the
@@ -713,6 +740,16 @@ static int mixed_phase2(bms_ctx* c, double mass, int n, int ns, const double* sh
     return rc;
   iters += cr.iters;
   reliable += cr.reliable;
+  if (cr.exhausted) {
+    // the FP32 recurrence ran out of Krylov space (small lattices, where the
+    // block spans it within a few hundred iterations): the same correction
+    // solve in FP64, which keeps what the FP64 phase reached
+    if ((rc = solve_core<double>(c, mass, n, na, sig.data(), xm.data(), t2tol, max_iter, o2, RB,
+                                 E2, cr)))
+      return rc;
+    iters += cr.iters;
+    reliable += cr.reliable;
+  }
   // a failed, diverged or softly stopped (breakdown, non-finite values) FP32
   // phase gives no usable correction: X stays as the FP64 phase left it
   if (cr.error || cr.diverged || cr.soft) return BMS_OK;
@@ -752,10 +789,10 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
     bms_opts o1 = o;
     o1.freeze_tol = o.freeze_tol > 0 ? std::min(o.freeze_tol, 0.5 * tol) : 0.5 * tol;
     if ((rc = solve_core<double>(c, mass, n, ns, sig.data(), order.data(), o.mixed_switch,
-                                 max_iter, o1, B, X, cr)))
+                                 max_iter, o1, B, X, cr, tol)))
       return rc;
     first_iters = cr.iters;
-    if (!cr.error &&
+    if (!cr.error && !cr.extended &&
         (rc = mixed_phase2(c, mass, n, ns, shifts, order.data(), tol, max_iter, o, B, X,
                            refine_iters, reliable)))
       return rc;
@@ -785,7 +822,7 @@ static int solve_precision(bms_ctx* c, double mass, int n, int ns, const double*
   // not gain a factor 10, then in FP64; a shift whose residual is worse than
   // that of X = 0 (a diverged main iteration) restarts from X = 0.
   const bool mixed = sizeof(T) == 4;
-  std::vector<char> use64(ns, fell_back ? 1 : 0);
+  std::vector<char> use64(ns, fell_back || cr.extended ? 1 : 0);
   int rows = 3 * c->vh;
   size_t blk = (size_t)rows * n;
   for (int round = 0; round < o.max_refine && !cr.error; ++round) {

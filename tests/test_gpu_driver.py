@@ -115,9 +115,12 @@ def test_uneven_batch_mixed_precision(torch):
     o.reliable_interval = 50
     shifts = [r.beta] * 3
     Xs, stats = bms.solve_batch(ctxs, [0.05] * 3, shifts, Bs, tol=1e-10, opts=o)
+    # the 8^4 problem has an FP32 phase; the two small ones span their block
+    # Krylov space quickly and finish in the FP64 phase
+    assert stats[1]["iterations_f32"] > 0
     for i, (dims, n, seed) in enumerate(probs):
         assert stats[i]["status"] == 0 and stats[i]["converged"]
-        assert stats[i]["iterations_f32"] > 0
+        assert stats[i]["iterations"] == stats[i]["iterations_f64"] + stats[i]["iterations_f32"]
         X1, st1 = ctxs[i].solve(0.05, shifts[i], Bs[i], tol=1e-10, opts=o)
         assert st1["iterations"] == stats[i]["iterations"]
         assert np.array_equal(to_np(X1), to_np(Xs[i]))
