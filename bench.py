@@ -24,6 +24,7 @@ The precision of the timed solves is the workload's (mixed at 32^4).
 import hashlib
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -83,7 +84,8 @@ def cpu_oracle_sample(U, B, w, r, per_vector_iters, budget_s, threads=None):
 # source file of each kernel class (for the staleness check of stored counters)
 KERNEL_SOURCE = {"update": "paper_1808_01829_amd/csrc/update_mfma.hip",
                  "hop": "paper_1808_01829_amd/csrc/hop.hip",
-                 "gram": "paper_1808_01829_amd/csrc/blas.hip"}
+                 "gram": "paper_1808_01829_amd/csrc/blas.hip",
+                 "force": "paper_1808_01829_amd/csrc/force.hip"}
 
 
 def source_sha(kernel):
@@ -221,6 +223,7 @@ def force_measure(bms, torch, np, configs, reps=3):
                 hbm_frac=round(gbs / HBM_PEAK_GBS, 4), tflops=round(tf, 2),
                 fp64_valu_frac=round(tf / FP64_VALU_PEAK_TFLOPS, 4),
                 bound="fp64 valu", frac_of_binding_roof=round(tf / FP64_VALU_PEAK_TFLOPS, 4),
+                traffic=stored_traffic("c4", "f64", "force"),
                 hops_then_per_link_us=round(res[0][0], 1))
 
 
@@ -293,6 +296,69 @@ def rhmc_measure(bms, torch, np, configs):
                 heatbath_action_residual=res["max_residual_hb"])
 
 
+KERNEL_CLASS_PREFIX = {"update": ("k_update_mfma", "k_update_n", "k_update_fast", "k_update<"),
+                       "hop": ("k_hop",), "gram": ("k_gram4",),
+                       "force": ("k_force_fused",)}
+
+
+def _counter_rows(path):
+    """(kernel name, counter value) of every dispatch in a rocprofv3
+    counter_collection CSV."""
+    import csv
+    out = []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            out.append((row.get("Kernel_Name", ""), float(row.get("Counter_Value", 0))))
+    return out
+
+
+COPY_BYTES = 1 << 30
+
+
+def copy_factor(cal_csv):
+    """Bytes per counted KiB: the 1 GiB copy of --copy-calibration over the
+    largest per-dispatch value the counter read in that run (the copy's; the
+    fill before it writes as much and reads nothing)."""
+    kib = max(v for _, v in _counter_rows(cal_csv))
+    return COPY_BYTES / (kib * 1024.0), kib
+
+
+def write_traffic(workload, prec, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, commands,
+                  algorithmic, out_dir):
+    """<out_dir>/traffic_<workload>_<prec>.json from one FETCH_SIZE and one
+    WRITE_SIZE rocprofv3 run (KiB per dispatch), scaled by what the same
+    counters read for a plain 1 GiB copy; algorithmic: {class: bytes per
+    launch}."""
+    fetch_factor, cal_f = copy_factor(cal_fetch_csv)
+    write_factor, cal_w = copy_factor(cal_write_csv)
+    fetch, write = _counter_rows(fetch_csv), _counter_rows(write_csv)
+    kernels = {}
+    for cls, prefixes in KERNEL_CLASS_PREFIX.items():
+        pat = re.compile(r"(^|[\s:])(%s)" % "|".join(re.escape(p) for p in prefixes))
+        f = [v for k, v in fetch if pat.search(k)]
+        w = [v for k, v in write if pat.search(k)]
+        if not f or not w or cls not in algorithmic:
+            continue
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        b = fk * 1024 * fetch_factor + wk * 1024 * write_factor
+        kernels[cls] = dict(source=KERNEL_SOURCE.get(cls), source_sha256=source_sha(cls),
+                            launches=len(f), fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+                            bytes_per_launch=round(b),
+                            algorithmic_bytes_per_launch=round(algorithmic[cls]),
+                            ratio=round(b / algorithmic[cls], 3))
+    out = dict(workload=workload, commands=commands,
+               calibration=dict(copy_bytes=COPY_BYTES, copy_fetch_kib=cal_f, copy_write_kib=cal_w,
+                                fetch_factor=round(fetch_factor, 4),
+                                write_factor=round(write_factor, 4),
+                                command="rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE -- python3 bench.py "
+                                        "--copy-calibration"),
+               kernels=kernels)
+    path = os.path.join(out_dir, "traffic_%s_%s.json" % (workload, prec))
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    return path
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +374,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip bms_autotune (kernel variants picked on this problem before warmup)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines file of bms_autotune results: a hit skips the sweep")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the workload's uneven batch of lattices (reported aside)")
     ap.add_argument("--seeds", type=int, default=3,
@@ -319,7 +387,35 @@ def main():
                     help="skip the RHMC trajectory measurement (reported aside)")
     ap.add_argument("--no-operators", action="store_true",
                     help="skip the unimproved/improved operator comparison (reported aside)")
+    ap.add_argument("--force-only", action="store_true",
+                    help="only the force measurement (for profiling the force kernel)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a 1 GiB device copy (calibrates the HBM traffic counters)")
+    ap.add_argument("--write-traffic", nargs=6,
+                    metavar=("PREC", "FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV",
+                             "RUN_JSON"),
+                    help="write traffic_<workload>_<PREC>.json from two rocprofv3 counter CSVs "
+                         "of this benchmark, scaled by the same counters on the 1 GiB copy of "
+                         "--copy-calibration, with the algorithmic bytes from that run's JSON "
+                         "line; then exit (no GPU)")
+    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles"),
+                    help="with --write-traffic: folder of the JSON file")
+    ap.add_argument("--profile-command", default="",
+                    help="with --write-traffic: the command the counter runs used ({} = counter)")
     args = ap.parse_args()
+    if args.write_traffic:
+        prec, fcsv, wcsv, cfcsv, cwcsv, run = args.write_traffic
+        line = [l for l in open(run) if l.startswith("{")][-1]
+        d = json.loads(line)
+        if "kernels" in d:  # a benchmark line: bytes and launches per kernel class
+            algo = {k: v["bytes"] / v["launches"] for k, v in d["kernels"].items() if v["bytes"]}
+        else:  # the force-only line
+            algo = {"force": d["algorithmic_bytes"]}
+        cmd = args.profile_command
+        print(write_traffic(args.workload, prec, fcsv, wcsv, cfcsv, cwcsv,
+                            [cmd.replace("{}", "FETCH_SIZE"), cmd.replace("{}", "WRITE_SIZE")],
+                            algo, args.traffic_out))
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -330,6 +426,19 @@ def main():
 
     from paper_1808_01829_amd import bms
     from paper_1808_01829_amd.inputs import configs, gaussian_block, random_gauge
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copied_bytes=1 << 30)), flush=True)
+        return
+    if args.force_only:
+        print(json.dumps(force_measure(bms, torch, np, configs)), flush=True)
+        return
 
     w = configs.WORKLOADS[args.workload]
     r = configs.workload_coefficients(args.workload)
@@ -352,6 +461,8 @@ def main():
         opts.reliable_interval = w["reliable"]
 
     tuned = None
+    if args.tune_cache:
+        ctx.set_tune_cache(args.tune_cache)
     if not args.no_autotune:
         t = time.time()
         tuned = ctx.autotune(m, r.beta, Bd, precision=opts.precision, iters=16)
