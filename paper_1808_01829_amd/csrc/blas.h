@@ -10,17 +10,19 @@
 template <typename T, typename TX>
 struct UpdateArgs {
   int rows, n, ns;
-  cplx<T>* Q;                 // [rows][n]  Q_{k-1} in, Q_k out
+  cplx<T>* Q;                 // [rows][n]  Q_{k-1} in, Q_k out (vector update, in place)
+  cplx<T>* Qring;             // matrix-core update: [win][rows][n], Q_j in buffer j % win
   const cplx<T>* W;           // [rows][n]  (A + s0) P^(0)
   const double2* alpha;       // n x n FP64
   const double2* rhoinv;      // n x n FP64
   cplx<T>* P;                 // [ns][rows][n] search directions, sorted shift order
-                              // (the matrix-core update: [2][ns][rows][n], buffer pp_cur[s])
   cplx<TX>* X;                // solutions; shift s at X + xidx[s]*rows*n
   const cplx<T>* Mx;          // [ns][n][n]
   const cplx<T>* Mp;          // [ns][n][n]
-  const cplx<T>* Mxd;         // [ns][n][n] the deferred Mx (matrix-core update)
-  SolverFlags* flags;         // read; the matrix-core update also sets upd_done
+  const cplx<T>* Wm;          // [ns][2][BMS_MAX_WIN][n][n] window coefficients (matrix cores)
+  const double2* wst;         // FP64 window state [2][ns][2][BMS_MAX_WIN][n][n] (drain)
+  int win;                    // window length of the shifts s >= 1 (1: every iteration)
+  SolverFlags* flags;         // read; the matrix-core update also sets upd_done, upd_stop
   int xidx[BMS_MAX_SHIFTS];
 };
 
@@ -37,13 +39,17 @@ hipError_t launch_update_fast(hipStream_t st, const UpdateArgs<T, TX>& a, int va
 // update on the matrix cores (update_mfma.hip), for n = 8 and 16, with one or
 // two 16-row tiles per wave; F = double or float (the Q step is FP64 in both)
 bool update_mfma_supported(int n);
-// With SmallParams::pingpong the shifts s >= 1 follow the PP_* modes the small
-// step sets; after the last iteration launch_update_drain adds every increment
-// still pending (Q, W, alpha, rhoinv and Mp are not used there).
+// The shifts s >= 1 are updated in windows of SmallParams::win iterations
+// (the small step gathers each window's coefficients, see SmallState::wst);
+// after the last iteration launch_update_drain applies every window still
+// open (Q, W, alpha, rhoinv, Mx and Mp are not used there).
 template <typename F>
 hipError_t launch_update_mfma(hipStream_t st, const UpdateArgs<F, F>& a, bool two_tiles);
 template <typename F>
 hipError_t launch_update_drain(hipStream_t st, const UpdateArgs<F, F>& a);
+// longest window the matrix-core update of precision F stages in LDS
+template <typename F>
+int update_mfma_max_win();
 hipError_t launch_resid_norms(hipStream_t st, int rows, int n, const void* B, const void* Y,
                               double2* out, double2* partials, int nb);
 hipError_t launch_action(hipStream_t st, int rows, int n, int ns, double a0, const double* alpha,
@@ -87,13 +93,20 @@ struct SmallState {
   double* rel_last; // smallest max relative true residual of sigma_0 at a reliable update
   int* counter;     // grid-completion counter of the rho kernel
   int* upd_log;    // [max_iter] block vectors the update of each iteration moves
+  // Window state of the deferred shift update, [2][ns][2][BMS_MAX_WIN][n*n]:
+  // per slot and shift the X family (Cx, Ex_0, Ex_1, ...) and the P family
+  // (Cp, Ep_0, ...) of the open window started at iteration k0, such that after
+  // iteration k (j = k - k0 + 1 iterations gathered)
+  //   X_{k+1} = X_k0 + P_k0 Cx + sum_{i < j-1} Q_{k0+1+i} Ex_i
+  //   P_{k+1} = Q_{k+1} + P_k0 Cp + sum_{i < j-1} Q_{k0+1+i} Ep_i
+  double2* wst;
 };
 
 struct SmallParams {
   int n, ns, max_iter;
   double tol, freeze_tol, breakdown_tol;
   double sigma[BMS_MAX_SHIFTS];  // sorted shifts
-  int pingpong;  // shifts s >= 1 take the two-iteration X update (matrix-core update)
+  int win;  // window of the shifts s >= 1 (matrix-core update; 1 = every iteration)
 };
 
 // initial QR of B: from G = B^H B, delta_0 = chol(G)^H, out Rinv = delta_0^-1;
@@ -106,12 +119,14 @@ hipError_t launch_small_init_pass2(hipStream_t st, const SmallParams& p, SmallSt
 // and Rinv_out = delta_k^-1 (so that Q_k = R0 Rinv_out)
 hipError_t launch_small_reliable(hipStream_t st, const SmallParams& p, SmallState s,
                                  SolverFlags* fl, const double2* Gin, double2* Rinv_out);
+// Wm: the window coefficients of every shift in the block precision, for the
+// matrix-core update ([ns][2][BMS_MAX_WIN][n*n], the layout of SmallState::wst)
 template <typename T>
 hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                             cplx<T>* Mx, cplx<T>* Mp, cplx<T>* Mxd);
+                             cplx<T>* Mx, cplx<T>* Mp, cplx<T>* Wm);
 template <typename T>
 hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
-                                     SolverFlags* fl, cplx<T>* Mp);
+                                     SolverFlags* fl, cplx<T>* Mp, cplx<T>* Wm);
 // variant 0: vector kernel; 1, 2 and the default: matrix cores, every wave
 // streaming its own rows with 4 or 8 steps in flight; 3, 4, 5: matrix cores,
 // rows staged through LDS with 1, 2 or 4 chunks in flight (n = 8, 16; other n

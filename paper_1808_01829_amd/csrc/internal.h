@@ -18,8 +18,8 @@ enum Slot {
   S_TMP = 0,  // odd-site temporary of bms_apply_mdagm
   S_W1,       // D_oe P^(0) (odd sites)
   S_W,        // (A + s0) P^(0)
-  S_Q,        // orthonormal residual block Q_k
-  S_P,        // directions P^(s), two buffers per shift for the two-iteration update
+  S_Q,        // orthonormal residual block Q_k (a ring of window-length buffers)
+  S_P,        // directions P^(s)
   S_X,        // solutions X^(s) in the block precision
   S_SMALL,    // n x n FP64 state of the recurrences
   S_PART,     // partial sums of the grid reductions
@@ -60,22 +60,18 @@ struct SolverFlags {
   int active[BMS_MAX_SHIFTS];  // shift still updated
   int conv[BMS_MAX_SHIFTS];    // shift converged at the last rho step
   double res[BMS_MAX_SHIFTS];  // max relative residual estimate per shift
-  // Two-iteration X^(s) update of the shifts s >= 1 (matrix-core update):
-  int pp_mode[BMS_MAX_SHIFTS];  // PP_* of this iteration's update
-  int pp_cur[BMS_MAX_SHIFTS];   // P^(s) buffer (0, 1) holding the current direction
-  int pp_pend[BMS_MAX_SHIFTS];  // X^(s) still lacks P^(s) of the other buffer times Mxd^(s)
-  int pp_done[BMS_MAX_SHIFTS];  // upd_done of the last update whose mode was applied
+  // Deferred update of the shifts (matrix-core update): per shift and slot
+  // (the iteration parity the small step writes for the update that follows
+  // it), the iterations gathered in the open window and whether the update
+  // applies them now.
+  int win_j[2][BMS_MAX_SHIFTS];
+  int win_flush[2][BMS_MAX_SHIFTS];
+  int upd_stop;  // stop as seen by the last matrix-core update that ran
 };
 
-// Update modes of one shift in one iteration (k = the iteration, P_k in the
-// buffer pp_cur, the other buffer holding P_{k-1} while an increment is pending):
-enum {
-  PP_NONE = 0,   // frozen, nothing pending
-  PP_NOW = 1,    // X += P_k Mx_k; P_k+1 = Q_k+1 + P_k Mp_k in place
-  PP_DEFER = 2,  // P_k+1 = Q_k+1 + P_k Mp_k into the other buffer; X waits (Mxd = Mx_k)
-  PP_FLUSH = 3,  // X += P_k-1 Mxd + P_k Mx_k; P_k+1 into the other buffer (over P_k-1)
-  PP_DRAIN = 4,  // frozen with an increment pending: X += P_k-1 Mxd
-};
+// Longest window of the deferred shift update (iterations gathered before the
+// update applies them) that the state arrays hold.
+constexpr int BMS_MAX_WIN = 8;
 
 // Traversal of the half hop for one precision: tiles of whole x-rows ty x tz
 // x tt in y, z, t (ty = 0: natural order; -1: the built-in choice for every

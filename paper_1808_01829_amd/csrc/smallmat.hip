@@ -214,11 +214,10 @@ __global__ __launch_bounds__(BMS_WG) void k_small_init(SmallParams p, SmallState
       fl->active[i] = i < p.ns;
       fl->conv[i] = 0;
       fl->res[i] = 1.0;
-      fl->pp_mode[i] = PP_NONE;
-      fl->pp_cur[i] = 0;
-      fl->pp_pend[i] = 0;
-      fl->pp_done[i] = -1;
+      fl->win_j[0][i] = fl->win_j[1][i] = 0;
+      fl->win_flush[0][i] = fl->win_flush[1][i] = 1;
     }
+  if (pass == 0 && threadIdx.x == 0) fl->upd_stop = 0;
   sm_load(L0, Gin, n);
   int st = sm_chol_upper(L1, L0, n, p.breakdown_tol);
   if (st) {
@@ -331,16 +330,12 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
   }
 }
 
-// Block vectors of one shift's update in a mode (see PP_*): P and X read and
-// written, or only P, or P twice and X, ...
-__device__ __forceinline__ int pp_traffic(int mode) {
-  return mode == PP_NOW ? 4 : mode == PP_DEFER ? 2 : mode == PP_FLUSH ? 5 : mode == PP_DRAIN ? 3 : 0;
-}
-
 // Completion of one iteration's small step: count this block's arrival and
 // whether its shift met tol; the last block to arrive stops the solve when
-// all did, logs the update's traffic (3 block vectors for the Q step plus each
-// shift's) and advances the iteration counter.
+// all did, logs the update's traffic and advances the iteration counter. The
+// update moves 3 block vectors for the Q step, 4 for each shift it applies
+// (P and X read and written) and, once, the ring buffers of the longest
+// window applied that are not in registers (Q_{k0+1} .. Q_{k-1}).
 __device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFlags* fl,
                              int done) {
   if (threadIdx.x == 0) {
@@ -349,8 +344,16 @@ __device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFl
     if ((v & 0xffff) == p.ns) {
       __threadfence();
       if ((v >> 16) == p.ns || fl->error) fl->stop = 1;
-      int units = 3;
-      for (int i = 0; i < p.ns; ++i) units += pp_traffic(fl->pp_mode[i]);
+      const int ws = (fl->iter + 1) & 1;
+      int units = 3, qx = 0;
+      for (int i = 0; i < p.ns; ++i) {
+        const int j = fl->win_j[ws][i];
+        if (j > 0 && (fl->win_flush[ws][i] || fl->stop)) {
+          units += 4;
+          qx = j - 2 > qx ? j - 2 : qx;
+        }
+      }
+      units += qx;
       if (s.upd_log && fl->iter < p.max_iter) s.upd_log[fl->iter] = units;
       fl->need_explicit = 0;
       fl->iter = fl->iter + 1;
@@ -359,13 +362,70 @@ __device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFl
   }
 }
 
+// C = C0 + A B (C0 = NULL: C = A B) for a stack of rows / n matrices A (rows x
+// n, global memory) and one n x n matrix B (LDS); C also goes to Ct in the
+// block precision.
+template <typename T>
+__device__ void win_mm(double2* C, const double2* C0, const double2* A, const double2* B,
+                       int rows, int n, cplx<T>* Ct) {
+  for (int e = threadIdx.x; e < rows * n; e += BMS_WG) {
+    int r = e / n, j = e - (e / n) * n;
+    double2 acc = C0 ? C0[e] : make_double2(0, 0);
+#pragma unroll 4
+    for (int k = 0; k < n; ++k) acc = cfma(A[r * n + k], B[k * n + j], acc);
+    C[e] = acc;
+    Ct[e] = from_d<cplx<T>>(acc);
+  }
+}
+
+// One iteration into shift q's update window (layout in SmallState::wst).
+// The window read is slot `cur` (what the previous small step wrote), the
+// one written slot cur ^ 1; a window that the last update applied (its flush
+// flag) starts again. With j0 iterations gathered, the new step's Mx, Mp give
+//   X family: [Cx, Ex_i] += [Cp, Ep_i] Mx, then Ex_{j0-1} = Mx (Q_k enters X)
+//   P family: [Cp, Ep_i]  = [Cp, Ep_i] Mp, then Ep_{j0-1} = Mp
+// (a fresh window: Cx = Mx, Cp = Mp). The update applies the window when it
+// holds `len` iterations (1 for sigma_0, whose P feeds the operator every
+// iteration) or the shift converged.
+template <typename T>
+__device__ void win_step(const SmallParams& p, const SmallState& s, SolverFlags* fl,
+                         cplx<T>* Wm, const double2* Mx, const double2* Mp, int q, int cur,
+                         bool conv_now) {
+  const int n = p.n, nn = n * n;
+  const int len = q == 0 ? 1 : p.win;
+  const int ws = cur ^ 1;
+  const int j0 = (fl->win_flush[cur][q] || fl->win_j[cur][q] == 0) ? 0 : fl->win_j[cur][q];
+  const size_t fam = (size_t)BMS_MAX_WIN * nn;
+  const double2* ox = s.wst + (size_t)(cur * p.ns + q) * 2 * fam;
+  const double2* op = ox + fam;
+  double2* nx = s.wst + (size_t)(ws * p.ns + q) * 2 * fam;
+  double2* np = nx + fam;
+  cplx<T>* tx = Wm + (size_t)q * 2 * fam;
+  cplx<T>* tp = tx + fam;
+  if (j0 > 0) {
+    win_mm<T>(nx, ox, op, Mx, j0 * n, n, tx);
+    win_mm<T>(np, nullptr, op, Mp, j0 * n, n, tp);
+  }
+  for (int e = threadIdx.x; e < nn; e += BMS_WG) {
+    nx[(size_t)j0 * nn + e] = Mx[e];
+    tx[(size_t)j0 * nn + e] = from_d<cplx<T>>(Mx[e]);
+    np[(size_t)j0 * nn + e] = Mp[e];
+    tp[(size_t)j0 * nn + e] = from_d<cplx<T>>(Mp[e]);
+  }
+  if (threadIdx.x == 0) {
+    fl->win_j[ws][q] = j0 + 1;
+    fl->win_flush[ws][q] = (j0 + 1 >= len) || conv_now;
+  }
+  __syncthreads();
+}
+
 // Everything that needs rho_k (in R, LDS): rho_k^-1, delta_k, the shift's
 // residual coefficients delta^(s)_k = rho_k alpha_k^-1 alpha^(s)_k, its update
 // matrix Mp and its convergence. Gk = G_k = alpha_k^-1 (LDS copy).
 template <typename T>
 __device__ void rho_part(const SmallParams& p, const SmallState& s, SolverFlags* fl, cplx<T>* Mp,
-                         const double2* R, const double2* Gk, double2* T0, double2* T1,
-                         double2* D, int q, int cur) {
+                         cplx<T>* Wm, const double2* R, const double2* Gk, double2* T0,
+                         double2* T1, double2* D, int q, int cur) {
   __shared__ double colmax;
   const int n = p.n, nn = n * n;
   if (q == 0) {
@@ -414,31 +474,15 @@ __device__ void rho_part(const SmallParams& p, const SmallState& s, SolverFlags*
       fl->halted = 1;
     }
   }
+  // the step into the shift's update window: Mx = alpha^(s)_k, Mp (FP64, T0)
+  if (q == 0)
+    for (int e = threadIdx.x; e < nn; e += BMS_WG) {
+      int i = e / n, j = e - (e / n) * n;
+      T0[e] = cconj(R[j * n + i]);
+    }
+  sm_load(T1, s.alpha_s + (size_t)q * nn, n);
+  win_step<T>(p, s, fl, Wm, T1, T0, q, cur, q > 0 && r < p.freeze_tol);
   finish_shift(p, s, fl, r < p.tol);
-}
-
-// Apply, once, what the last update that ran did to shift q's direction
-// buffers and pending increment (its mode is still in pp_mode[q]): a deferred
-// step keeps its Mx as Mxd and flips the buffer, a flush flips it and clears
-// the pending increment, a drain clears it. An update that was skipped (the
-// solve halted after this step) changed nothing and is not applied.
-template <typename C>
-__device__ void pp_commit(SolverFlags* fl, int q, const C* Mx, C* Mxd, int nn) {
-  const int u = fl->upd_done;
-  const int done = fl->pp_done[q];
-  const int m = fl->pp_mode[q];
-  __syncthreads();  // every thread has read the flags before thread 0 writes them
-  if (u == done) return;
-  if (m == PP_DEFER)
-    for (int e = threadIdx.x; e < nn; e += BMS_WG) Mxd[(size_t)q * nn + e] = Mx[(size_t)q * nn + e];
-  if (threadIdx.x == 0) {
-    if (m == PP_DEFER || m == PP_FLUSH) fl->pp_cur[q] ^= 1;
-    if (m == PP_DEFER) fl->pp_pend[q] = 1;
-    if (m == PP_FLUSH || m == PP_DRAIN) fl->pp_pend[q] = 0;
-    fl->pp_mode[q] = PP_NONE;
-    fl->pp_done[q] = u;
-  }
-  __syncthreads();  // Mx is overwritten after the copy
 }
 
 // One iteration's n x n work, after G4 = [P^H W, Q^H W, W^H W, Q^H Q]:
@@ -449,7 +493,7 @@ __device__ void pp_commit(SolverFlags* fl, int q, const C* Mx, C* Mxd, int nn) {
 template <typename T>
 __global__ __launch_bounds__(BMS_WG) void k_small_iter(SmallParams p, SmallState s,
                                                        SolverFlags* fl, cplx<T>* Mx,
-                                                       cplx<T>* Mp, cplx<T>* Mxd) {
+                                                       cplx<T>* Mp, cplx<T>* Wm) {
   __shared__ double2 Gk[NN], A[NN], R[NN], T0[NN], T1[NN], T2[NN], T3[NN];
   const int n = p.n, nn = n * n;
   const int q = blockIdx.x;
@@ -461,20 +505,16 @@ __global__ __launch_bounds__(BMS_WG) void k_small_iter(SmallParams p, SmallState
     return;
   }
   const int cur = fl->iter & 1, prev = cur ^ 1;
-  pp_commit(fl, q, Mx, Mxd, nn);
   if (q > 0 && (fl->conv[q] || !fl->active[q])) {
+    // frozen: its last window was applied when it converged
     if (threadIdx.x == 0) {
       fl->active[q] = 0;
-      fl->pp_mode[q] = fl->pp_pend[q] ? PP_DRAIN : PP_NONE;
+      fl->win_j[prev][q] = 0;
+      fl->win_flush[prev][q] = 1;
     }
     finish_shift(p, s, fl, 1);
     return;
   }
-  // this iteration's update of the shift: every iteration for sigma_0 (its P
-  // feeds the operator, its X the reliable updates), else deferred and
-  // flushed in turn
-  if (threadIdx.x == 0)
-    fl->pp_mode[q] = (q == 0 || !p.pingpong) ? PP_NOW : (fl->pp_pend[q] ? PP_FLUSH : PP_DEFER);
   sm_load(Gk, s.G4, n);
   int st = sm_chol_upper(T0, Gk, n, 0.0);
   if (st) {
@@ -559,13 +599,14 @@ __global__ __launch_bounds__(BMS_WG) void k_small_iter(SmallParams p, SmallState
     }
     return;
   }
-  rho_part<T>(p, s, fl, Mp, R, Gk, T0, T1, T2, q, cur);
+  rho_part<T>(p, s, fl, Mp, Wm, R, Gk, T0, T1, T2, q, cur);
 }
 
 // Fallback when the expansion lost accuracy: rho_k from the explicit V^H V.
 template <typename T>
 __global__ __launch_bounds__(BMS_WG) void k_small_rho_explicit(SmallParams p, SmallState s,
-                                                               SolverFlags* fl, cplx<T>* Mp) {
+                                                               SolverFlags* fl, cplx<T>* Mp,
+                                                               cplx<T>* Wm) {
   __shared__ double2 Gk[NN], R[NN], T0[NN], T1[NN], T2[NN];
   const int n = p.n;
   const int q = blockIdx.x;
@@ -579,7 +620,7 @@ __global__ __launch_bounds__(BMS_WG) void k_small_rho_explicit(SmallParams p, Sm
     return;
   }
   sm_load(Gk, s.G4, n);
-  rho_part<T>(p, s, fl, Mp, R, Gk, T0, T1, T2, q, cur);
+  rho_part<T>(p, s, fl, Mp, Wm, R, Gk, T0, T1, T2, q, cur);
 }
 
 }  // namespace
@@ -604,15 +645,15 @@ hipError_t launch_small_reliable(hipStream_t st, const SmallParams& p, SmallStat
 
 template <typename T>
 hipError_t launch_small_iter(hipStream_t st, const SmallParams& p, SmallState s, SolverFlags* fl,
-                             cplx<T>* Mx, cplx<T>* Mp, cplx<T>* Mxd) {
-  k_small_iter<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mx, Mp, Mxd);
+                             cplx<T>* Mx, cplx<T>* Mp, cplx<T>* Wm) {
+  k_small_iter<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mx, Mp, Wm);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, SmallState s,
-                                     SolverFlags* fl, cplx<T>* Mp) {
-  k_small_rho_explicit<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mp);
+                                     SolverFlags* fl, cplx<T>* Mp, cplx<T>* Wm) {
+  k_small_rho_explicit<T><<<p.ns, BMS_WG, 0, st>>>(p, s, fl, Mp, Wm);
   return hipGetLastError();
 }
 
@@ -620,6 +661,6 @@ hipError_t launch_small_rho_explicit(hipStream_t st, const SmallParams& p, Small
   template hipError_t launch_small_iter<T>(hipStream_t, const SmallParams&, SmallState,     \
                                            SolverFlags*, C*, C*, C*);                       \
   template hipError_t launch_small_rho_explicit<T>(hipStream_t, const SmallParams&,         \
-                                                   SmallState, SolverFlags*, C*);
+                                                   SmallState, SolverFlags*, C*, C*);
 INST_SMALL(double, double2)
 INST_SMALL(float, float2)

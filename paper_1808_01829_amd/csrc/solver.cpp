@@ -40,8 +40,9 @@ size_t part_bytes(int nb, int P) { return (size_t)nb * P * sizeof(double2) + 64;
 
 struct Work {
   int rows, n, ns;
+  int win;     // update window of the shifts s >= 1 (1: every iteration)
   size_t blk;  // complex elements per block vector
-  void *W1, *W, *Q, *P, *X, *Mx, *Mp, *Mxd;
+  void *W1, *W, *Q, *P, *X, *Mx, *Mp, *Wm;
   SmallState sm;
   SolverFlags* flags;
   double2* partials;
@@ -50,31 +51,46 @@ struct Work {
   int nb;
 };
 
-// The matrix-core update with the two-iteration X update of the shifts s >= 1
-// (update variants -1, 4, 5 at n = 8, 16; 6 updates every shift every iteration).
-bool use_pingpong(const bms_ctx* c, int n) {
+// Update window of the shifts s >= 1: the matrix-core update (variants -1, 4,
+// 5 at n = 8, 16) applies each shift's X and P updates once per window of
+// iterations; its length is the longest the kernel stages (4 in FP64, 8 in
+// FP32) that divides the chunk of iterations between host checks, so that
+// every window closes at a chunk's end (where the mixed solver's reliable
+// update needs every X). Variant 6, the vector kernels and one shift: 1.
+int update_window(const bms_ctx* c, int n, int ns, int elem_bytes, int check_interval) {
   const int uv = c->update_variant;
-  return update_mfma_supported(n) && (uv < 0 || uv == 4 || uv == 5);
+  if (ns < 2 || !update_mfma_supported(n) || !(uv < 0 || uv == 4 || uv == 5)) return 1;
+  int w = elem_bytes == 8 ? update_mfma_max_win<double>() : update_mfma_max_win<float>();
+  w = std::min(w, BMS_MAX_WIN);
+  while (w > 1 && check_interval % w) w >>= 1;
+  return w;
+}
+
+// n x n FP64 entries of the small state (SmallState), the window state included
+size_t small_elems(int n, int ns) {
+  const size_t nn = (size_t)n * n;
+  return 2 * nn + 2 * nn + 8 * nn + 2 * ns * nn + 3 * nn + n + 1 +
+         (size_t)2 * ns * 2 * BMS_MAX_WIN * nn;
 }
 
 template <typename T>
-int alloc_work(bms_ctx* c, int n, int ns, int max_iter, bool pingpong, Work& w) {
+int alloc_work(bms_ctx* c, int n, int ns, int max_iter, int win, Work& w) {
   int rc;
   w.n = n;
   w.ns = ns;
+  w.win = win;
   w.rows = 3 * c->vh;
   w.blk = (size_t)w.rows * n;
   size_t es = sizeof(cplx<T>);
   if ((rc = scratch_buf(c, S_W1, w.blk * es, &w.W1))) return rc;
   if ((rc = scratch_buf(c, S_W, w.blk * es, &w.W))) return rc;
-  if ((rc = scratch_buf(c, S_Q, w.blk * es, &w.Q))) return rc;
-  // two direction buffers per shift for the two-iteration update
-  if ((rc = scratch_buf(c, S_P, w.blk * es * ns * (pingpong ? 2 : 1), &w.P))) return rc;
+  // Q_j in ring buffer j % win
+  if ((rc = scratch_buf(c, S_Q, w.blk * es * win, &w.Q))) return rc;
+  if ((rc = scratch_buf(c, S_P, w.blk * es * ns, &w.P))) return rc;
   if ((rc = scratch_buf(c, S_X, w.blk * es * ns, &w.X))) return rc;
   size_t nn = (size_t)n * n;
-  size_t small_elems = 2 * nn + 2 * nn + 8 * nn + 2 * ns * nn + 3 * nn + n + 1;
   void* sp;
-  if ((rc = scratch_buf(c, S_SMALL, small_elems * sizeof(double2) + 64, &sp))) return rc;
+  if ((rc = scratch_buf(c, S_SMALL, small_elems(n, ns) * sizeof(double2) + 64, &sp))) return rc;
   double2* d = (double2*)sp;
   w.sm.Gb = d;
   d += 2 * nn;
@@ -102,15 +118,17 @@ int alloc_work(bms_ctx* c, int n, int ns, int max_iter, bool pingpong, Work& w) 
   d += nn;
   w.sm.norm0 = (double*)d;
   w.sm.rel_last = (double*)d + n;
+  d += n + 1;
+  w.sm.wst = d;
   w.nb = gram_blocks(w.rows, n, c->num_cu);
   void* pp;
   if ((rc = scratch_buf(c, S_PART, part_bytes(w.nb, 4 * nn), &pp))) return rc;
   w.partials = (double2*)pp;
   void* mp;
-  if ((rc = scratch_buf(c, S_M, 3 * ns * nn * es, &mp))) return rc;
+  if ((rc = scratch_buf(c, S_M, (2 + 2 * BMS_MAX_WIN) * ns * nn * es, &mp))) return rc;
   w.Mx = mp;
   w.Mp = (char*)mp + ns * nn * es;
-  w.Mxd = (char*)mp + 2 * ns * nn * es;
+  w.Wm = (char*)mp + 2 * ns * nn * es;
   void* fp;
   if ((rc = scratch_buf(c, S_FLAGS, kFlagsBytes, &fp))) return rc;
   w.flags = (SolverFlags*)fp;
@@ -132,6 +150,7 @@ UpdateArgs<T, T> update_args(const Work& w) {
   ua.n = w.n;
   ua.ns = w.ns;
   ua.Q = (cplx<T>*)w.Q;
+  ua.Qring = (cplx<T>*)w.Q;
   ua.W = (const cplx<T>*)w.W;
   ua.alpha = w.sm.alpha;
   ua.rhoinv = w.sm.rhoinv;
@@ -139,7 +158,9 @@ UpdateArgs<T, T> update_args(const Work& w) {
   ua.X = (cplx<T>*)w.X;
   ua.Mx = (const cplx<T>*)w.Mx;
   ua.Mp = (const cplx<T>*)w.Mp;
-  ua.Mxd = (const cplx<T>*)w.Mxd;
+  ua.Wm = (const cplx<T>*)w.Wm;
+  ua.wst = w.sm.wst;
+  ua.win = w.win;
   ua.flags = w.flags;
   for (int s = 0; s < BMS_MAX_SHIFTS; ++s) ua.xidx[s] = s < w.ns ? s : 0;
   return ua;
@@ -148,11 +169,13 @@ UpdateArgs<T, T> update_args(const Work& w) {
 // ev: NULL, or 8 timing events recorded around the 7 launches (direct
 // launches only: event-record nodes of a replayed graph carry no usable
 // timestamps on this runtime, measured).
+// k: the iteration's index (Q_k is in ring buffer k % win).
 template <typename T>
-int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
+int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double mass, long k,
                       hipEvent_t* ev) {
   const int* skip = &w.flags->stop;
   cplx<T>* P0 = (cplx<T>*)w.P;
+  const cplx<T>* Qk = (const cplx<T>*)w.Q + (size_t)(k % w.win) * w.blk;
 #define MARK(i) \
   if (ev) HIP_TRY(c, hipEventRecord(ev[i], c->stream))
   MARK(0);
@@ -160,17 +183,18 @@ int enqueue_iteration(bms_ctx* c, const Work& w, const SmallParams& sp, double m
   MARK(1);
   HIP_TRY(c, launch_hop<T>(c, 0, w.n, w.W1, w.W, P0, mass * mass + sp.sigma[0], -1.0, skip));
   MARK(2);
-  HIP_TRY(c, launch_gram4<T>(c->stream, w.rows, w.n, P0, w.Q, w.W, w.sm.G4, w.partials, w.nb,
+  HIP_TRY(c, launch_gram4<T>(c->stream, w.rows, w.n, P0, Qk, w.W, w.sm.G4, w.partials, w.nb,
                              skip, c->gram_variant, c->num_cu));
   MARK(3);
   HIP_TRY(c, launch_small_iter<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mx,
-                                  (cplx<T>*)w.Mp, (cplx<T>*)w.Mxd));
+                                  (cplx<T>*)w.Mp, (cplx<T>*)w.Wm));
   MARK(4);
   // explicit Cholesky-QR Gram, only when the expansion lost its pivot
-  HIP_TRY(c, launch_cholqr_gram<T>(c->stream, w.rows, w.n, w.Q, w.W, w.sm.alpha, w.sm.Gqr,
+  HIP_TRY(c, launch_cholqr_gram<T>(c->stream, w.rows, w.n, Qk, w.W, w.sm.alpha, w.sm.Gqr,
                                    w.partials, w.nb, &w.flags->need_explicit));
   MARK(5);
-  HIP_TRY(c, launch_small_rho_explicit<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mp));
+  HIP_TRY(c, launch_small_rho_explicit<T>(c->stream, sp, w.sm, w.flags, (cplx<T>*)w.Mp,
+                                          (cplx<T>*)w.Wm));
   MARK(6);
   const UpdateArgs<T, T> ua = update_args<T>(w);
   // built-in default: the matrix-core kernel where it exists (n = 8, 16), else
@@ -208,6 +232,7 @@ int enqueue_setup(bms_ctx* c, const Work& w, const SmallParams& sp, const void* 
 
 // MIXED: FP32 increments into the FP64 solutions, then the unshifted true
 // residual replaces the iterated one.
+// (Called between chunks of iterations, where Q_k is in ring buffer 0.)
 int enqueue_reliable(bms_ctx* c, const Work& w, const SmallParams& sp, double mass, const void* B,
                      void* Xout, const int* xmap, void* R1, void* R2, void* R0, bool flush_only) {
   const int* skip = &w.flags->stop;
@@ -252,7 +277,7 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
   } k;
   memset(&k, 0, sizeof k);
   const void* ptrs[16] = {w.W1, w.W, w.Q, w.P, w.X, w.Mx, w.Mp, w.flags, w.partials, w.sm.counter,
-                          c->links64.p, c->links32.p, nullptr, nullptr, nullptr, nullptr};
+                          c->links64.p, c->links32.p, w.Wm, w.sm.wst, nullptr, nullptr};
   for (int i = 0; i < 16; ++i) k.p[i] = ptrs[i];
   k.mass = mass;
   k.K = K;
@@ -279,7 +304,9 @@ int enqueue_chunk(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
                   bool use_graph) {
   if (!use_graph || c->timing) {
     for (int k = 0; k < K; ++k) {
-      int rc = enqueue_iteration<T>(c, w, sp, mass, c->timing ? &c->evpool[8 * k] : nullptr);
+      // chunks start at multiples of K, which win divides: k % win is the
+      // iteration's ring position
+      int rc = enqueue_iteration<T>(c, w, sp, mass, k, c->timing ? &c->evpool[8 * k] : nullptr);
       if (rc) return rc;
     }
     return BMS_OK;
@@ -295,7 +322,7 @@ int enqueue_chunk(bms_ctx* c, const Work& w, const SmallParams& sp, double mass,
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = BMS_OK;
     for (int k = 0; k < K && rc == BMS_OK; ++k)
-      rc = enqueue_iteration<T>(c, w, sp, mass, nullptr);
+      rc = enqueue_iteration<T>(c, w, sp, mass, k, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rc) {
@@ -346,9 +373,9 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
   // block vectors' precision (FP32 blocks in the mixed solver)
   sp.breakdown_tol = 10.0 * n * (mixed ? kEps32 : kEps);
   for (int s = 0; s < ns; ++s) sp.sigma[s] = sigma[s];
-  sp.pingpong = ns > 1 && use_pingpong(c, n);
+  sp.win = update_window(c, n, ns, (int)sizeof(T), o.check_interval);
   Work w;
-  if ((rc = alloc_work<T>(c, n, ns, max_iter, sp.pingpong != 0, w))) return rc;
+  if ((rc = alloc_work<T>(c, n, ns, max_iter, sp.win, w))) return rc;
   void *R1 = nullptr, *R2 = nullptr, *R0 = nullptr;
   if (mixed) {
     size_t b64 = w.blk * sizeof(double2);
@@ -409,7 +436,8 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
       return set_err(c, BMS_EHIP, "device iteration control did not stop (iter %d)", hf.iter);
   }
   // increments the two-iteration update still holds back
-  if (sp.pingpong) HIP_TRY(c, launch_update_drain<T>(c->stream, update_args<T>(w)));
+  // windows the solve ended with still open
+  if (w.win > 1) HIP_TRY(c, launch_update_drain<T>(c->stream, update_args<T>(w)));
   if (c->timing && hf.iter > 0) {
     std::vector<int> units(hf.iter);
     HIP_TRY(c, hipMemcpyAsync(units.data(), w.sm.upd_log, hf.iter * sizeof(int),
@@ -480,13 +508,14 @@ int solve_reserve(bms_ctx* c, double mass, int n, int ns, const double* shifts, 
   } need[] = {
       {S_W1, blk * e},
       {S_W, blk * e},
-      {S_Q, blk * e},
-      {S_P, blk * e * ns * 2},
+      {S_Q, blk * std::max(e * update_window(c, n, ns, 8, check_interval),
+                           sizeof(float2) * update_window(c, n, ns, 4, check_interval))},
+      {S_P, blk * e * ns},
       {S_X, blk * e * ns},
-      {S_SMALL, (17 * nn + 2 * ns * nn + n + 1) * e + 64},
+      {S_SMALL, small_elems(n, ns) * e + 64},
       {S_PART, std::max(part_bytes(gram_blocks((int)rows, n, c->num_cu), 4 * (int)nn),
                         part_bytes(gram_blocks((int)rows, 1, c->num_cu), 4))},
-      {S_M, 3 * ns * nn * e},
+      {S_M, (2 + 2 * BMS_MAX_WIN) * ns * nn * e},
       {S_FLAGS, kFlagsBytes},
       {S_LOG, (size_t)max_iter * sizeof(int) + 64},
       {S_R1, blk * e},

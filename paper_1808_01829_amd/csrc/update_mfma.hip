@@ -180,51 +180,73 @@ __device__ __forceinline__ void mfma_acc(typename Mf<F>::V (&d)[MfShape<N>::NT],
     for (int nt = 0; nt < S::NT; ++nt) d[nt] = Mf<F>::mfma(a[ks], b[ks][nt], d[nt]);
 }
 
+// Longest window of the deferred shift update whose coefficients (2 x window
+// complex n x n matrices of one shift) the kernel stages in LDS: 32 KiB at
+// n = 16 in either precision.
+template <typename F>
+struct MfWin {
+  static constexpr int MW = sizeof(F) == 8 ? 4 : 8;
+};
+
 // F: block and shift-update arithmetic type (double, or float in the mixed
 // solver). NTILE: 16-row tiles per wave (processed one after the other inside
-// each shift). The shifts to update come from one ballot over their modes
-// (PP_*); the tiles of the next such shift are loaded into the registers the
-// current tile has just stored from, so they are in flight during the next
-// shift's expansion and barrier. Per mode a shift moves 4 (PP_NOW), 2
-// (PP_DEFER: P only), 5 (PP_FLUSH: both directions, X and the new direction)
-// or 3 (PP_DRAIN) block vectors: 7 every two iterations where the plain
-// update moves 8.
-// FP32 blocks, one tile per wave: four waves per SIMD or more (the register
-// count the compiler picks by itself leaves fewer; at 32^4 the mixed solve
-// took 7.26 instead of 7.38 s). In FP64 four waves need spills, whose scratch
-// traffic reached HBM (6-9 % over the algorithmic bytes) for no gain in time,
-// so FP64 keeps three.
+// each shift).
+//
+// The Q step reads Q_k from ring buffer k % win and writes Q_{k+1} to
+// buffer (k+1) % win (in place for win = 1). Then every shift whose update
+// window the small step closed (or, when the solve stops here, every open
+// one) is applied, with j iterations in its window:
+//   X += P Cx + sum_{i < j-1} Q_{k-j+2+i} Ex_i
+//   P  = Q_{k+1} + P Cp + sum_{i < j-1} Q_{k-j+2+i} Ep_i     (in place)
+// (sigma_0: j = 1 every iteration, the plain X += P Mx, P = Q + P Mp). A
+// shift moves 4 block vectors per window instead of 4 per iteration; the
+// ring buffers it also reads are the same for every shift, so after the
+// first shift of a tile they come from L2.
+// One tile per wave: four waves per SIMD in FP32, three in FP64 (the register
+// count the compiler picks by itself leaves fewer; in FP64 four waves need
+// spills, whose scratch traffic reached HBM).
 template <typename F, int N, int NTILE>
 __global__ __launch_bounds__(BMS_WG)
-__attribute__((amdgpu_waves_per_eu(NTILE == 1 && sizeof(F) == 4 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(NTILE == 1 ? (sizeof(F) == 4 ? 4 : 3) : 1)))
 void k_update_mfma(UpdateArgs<F, F> a) {
   using S = MfShape<N>;
   using CF = cplx<F>;
   using VF = typename Mf<F>::V;
+  constexpr int MW = MfWin<F>::MW;
   // LDS: the Q-step operands (FP64) and the complex staging, then (FP32) the
-  // per-wave layout change of Q, then the double-buffered shift operands (F)
+  // per-wave layout change of Q, then one shift's window coefficients (F)
   constexpr int QBYTES = 2 * S::BSZ * 8 + 2 * N * N * 16;
   constexpr int TBYTES = MF_WAVES * NTILE * 16 * S::NR * 8;
-  constexpr int SBYTES = 2 * 3 * 2 * N * N * (int)sizeof(F);
+  constexpr int SBYTES = 2 * MW * 2 * N * N * (int)sizeof(F);
   constexpr int LBYTES = QBYTES > SBYTES ? (QBYTES > TBYTES ? QBYTES : TBYTES)
                                          : (SBYTES > TBYTES ? SBYTES : TBYTES);
   __shared__ __align__(16) unsigned char lds[LBYTES];
   double* qb0 = (double*)lds;
   double* qb1 = qb0 + S::BSZ;
   double2* cs = (double2*)(qb1 + S::BSZ);  // alpha, rho^-1
-  F* sb = (F*)lds;                         // [2][3][N*N] complex
+  F* sb = (F*)lds;                         // [2][MW][N*N] complex: X family, then P family
   SolverFlags* fl = a.flags;
   if (fl->halted) return;
   const int tid = threadIdx.x;
-  // the next small step applies this update's modes (nothing else in this
-  // kernel reads upd_done)
-  if (blockIdx.x == 0 && tid == 0) fl->upd_done = fl->iter;
+  const int iter = fl->iter;  // k + 1: the small step of iteration k has counted it
+  const int stop = fl->stop;
+  const int slot = iter & 1;
+  // the next small step and the drain read these (nothing else in this
+  // kernel reads them)
+  if (blockIdx.x == 0 && tid == 0) {
+    fl->upd_done = iter;
+    fl->upd_stop = stop;
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
-  const int rows = a.rows, ns = a.ns;
+  const int rows = a.rows, ns = a.ns, win = a.win;
   const size_t blk = (size_t)rows * N;
+  const int k = iter - 1;
+  const CF* Qin = a.Qring + (size_t)(k % win) * blk;
+  CF* Qout = a.Qring + (size_t)((k + 1) % win) * blk;
   const int tile0 = (blockIdx.x * MF_WAVES + wave) * NTILE;
-  unsigned long long mask = __ballot(lane < ns && fl->pp_mode[lane] != PP_NONE);
+  unsigned long long mask =
+      __ballot(lane < ns && fl->win_j[slot][lane] > 0 && (fl->win_flush[slot][lane] || stop));
 
   // coefficients of the Q step: B0 = rho^-1, B1 = -alpha rho^-1
   for (int e = tid; e < N * N; e += BMS_WG) {
@@ -235,7 +257,7 @@ void k_update_mfma(UpdateArgs<F, F> a) {
   for (int e = tid; e < N * N; e += BMS_WG) {
     int i = e / N, j = e - (e / N) * N;
     double2 t = make_double2(0.0, 0.0);
-    for (int k = 0; k < N; ++k) t = cfma(cs[i * N + k], cs[N * N + k * N + j], t);
+    for (int kk = 0; kk < N; ++kk) t = cfma(cs[i * N + kk], cs[N * N + kk * N + j], t);
     bput<N>(qb0, i, j, cs[N * N + e]);
     bput<N>(qb1, i, j, make_double2(-t.x, -t.y));
   }
@@ -247,7 +269,7 @@ void k_update_mfma(UpdateArgs<F, F> a) {
 #pragma unroll
     for (int t = 0; t < NTILE; ++t) {
       const int r0 = (tile0 + t) * 16;
-      aload<N>(a.Q, r0 + c, rows, g, av[t]);
+      aload<N>(Qin, r0 + c, rows, g, av[t]);
       aload<N>(a.W, r0 + c, rows, g, wv[t]);
     }
     bload<N>(qb0, lane, b0);
@@ -261,8 +283,9 @@ void k_update_mfma(UpdateArgs<F, F> a) {
     }
   }
   // every lane of the wave has read its Q tiles before any is overwritten
+  // (win = 1: Q_{k+1} replaces Q_k in place)
 #pragma unroll
-  for (int t = 0; t < NTILE; ++t) dstore<N, double>(a.Q, (tile0 + t) * 16, rows, g, c, qd[t]);
+  for (int t = 0; t < NTILE; ++t) dstore<N, double>(Qout, (tile0 + t) * 16, rows, g, c, qd[t]);
   __syncthreads();  // the Q-step LDS is reused below
   // Q_{k+1} in the shift-update layout and precision: the same registers in
   // FP64; in FP32 rounded and moved to the f32 row mapping through LDS
@@ -289,58 +312,42 @@ void k_update_mfma(UpdateArgs<F, F> a) {
 #pragma unroll
         for (int p = 0; p < 4; ++p)
           qn[t][nt][p] = (F)tq[(t * 16 + Mf<F>::row(g, p)) * S::NR + nt * 16 + c];
-    __syncthreads();  // the shift operands overwrite this LDS
+    __syncthreads();  // the shift coefficients overwrite this LDS
   }
 
-  // direction buffer b of shift s, and the tiles a shift's mode reads
-  auto pbuf = [&](int s, int b) { return a.P + ((size_t)b * ns + s) * blk; };
-  F pa[NTILE][S::KS], pb[NTILE][S::KS];
+  // the P and X tiles of a shift (the next shift's are loaded while the
+  // current one finishes)
+  F pa[NTILE][S::KS];
   VF xa[NTILE][S::NT];
   auto fetch = [&](int s, int t) {
-    const int m = __builtin_amdgcn_readfirstlane(fl->pp_mode[s]);
-    const int cb = __builtin_amdgcn_readfirstlane(fl->pp_cur[s]);
     const int r0 = (tile0 + t) * 16;
-    if (m != PP_DRAIN) aload<N>(pbuf(s, cb), r0 + c, rows, g, pa[t]);
-    if (m == PP_FLUSH || m == PP_DRAIN) aload<N>(pbuf(s, cb ^ 1), r0 + c, rows, g, pb[t]);
-    if (m != PP_DEFER) dload<N, F>(a.X + (size_t)a.xidx[s] * blk, r0, rows, g, c, xa[t]);
+    aload<N>(a.P + (size_t)s * blk, r0 + c, rows, g, pa[t]);
+    dload<N, F>(a.X + (size_t)a.xidx[s] * blk, r0, rows, g, c, xa[t]);
   };
   int s = mask ? __ffsll((long long)mask) - 1 : -1;
   if (s >= 0) {
 #pragma unroll
     for (int t = 0; t < NTILE; ++t) fetch(s, t);
   }
-  int buf = 0;
+  constexpr size_t FAM = (size_t)BMS_MAX_WIN * N * N;  // one family in Wm
   while (s >= 0) {
     mask &= mask - 1;
     const int s2 = mask ? __ffsll((long long)mask) - 1 : -1;
-    const int m = __builtin_amdgcn_readfirstlane(fl->pp_mode[s]);
-    const int cb = __builtin_amdgcn_readfirstlane(fl->pp_cur[s]);
-    const bool take_x = m == PP_NOW || m == PP_FLUSH;   // X += P_k Mx_k
-    const bool take_d = m == PP_FLUSH || m == PP_DRAIN;  // X += P_k-1 Mxd
-    const bool new_p = m != PP_DRAIN;                    // P_k+1 = Q_k+1 + P_k Mp_k
-    F* bx = sb + (3 * buf) * 2 * N * N;
-    F* bp = bx + 2 * N * N;
-    F* bd = bp + 2 * N * N;
-    const CF* mx = a.Mx + (size_t)s * N * N;
-    const CF* mp = a.Mp + (size_t)s * N * N;
-    const CF* md = a.Mxd + (size_t)s * N * N;
-    for (int e = tid; e < N * N; e += BMS_WG) {
-      if (take_x) {
-        bx[2 * e] = mx[e].x;
-        bx[2 * e + 1] = mx[e].y;
-      }
-      if (new_p) {
-        bp[2 * e] = mp[e].x;
-        bp[2 * e + 1] = mp[e].y;
-      }
-      if (take_d) {
-        bd[2 * e] = md[e].x;
-        bd[2 * e + 1] = md[e].y;
-      }
+    const int j = __builtin_amdgcn_readfirstlane(fl->win_j[slot][s]);
+    // the window's 2j coefficient matrices into LDS
+    const CF* wm = a.Wm + (size_t)s * 2 * FAM;
+    for (int e = tid; e < j * N * N; e += BMS_WG) {
+      const CF vx = wm[e], vp = wm[FAM + e];
+      sb[2 * e] = vx.x;
+      sb[2 * e + 1] = vx.y;
+      sb[2 * MW * N * N + 2 * e] = vp.x;
+      sb[2 * MW * N * N + 2 * e + 1] = vp.y;
     }
     __syncthreads();
+    const F* bx = sb;
+    const F* bp = sb + 2 * MW * N * N;
     CF* X = a.X + (size_t)a.xidx[s] * blk;
-    CF* Pout = pbuf(s, m == PP_NOW ? cb : cb ^ 1);
+    CF* P = a.P + (size_t)s * blk;
 #pragma unroll
     for (int t = 0; t < NTILE; ++t) {
       const int r0 = (tile0 + t) * 16;
@@ -350,57 +357,67 @@ void k_update_mfma(UpdateArgs<F, F> a) {
         pn[nt] = qn[t][nt];
         dx[nt] = VF{0, 0, 0, 0};
       }
-      // the increment (one or two iterations') is formed on its own and added
-      // to X once, so X (large next to one step's increment) is rounded once
-      if (take_d) mfma_acc_c<N>(dx, pb[t], bd, g, c);
-      if (take_x) mfma_acc_c<N>(dx, pa[t], bx, g, c);
-      if (new_p) mfma_acc_c<N>(pn, pa[t], bp, g, c);
-      if (m != PP_DEFER) {
+      // ring buffers Q_{k-j+2} .. Q_k, two in flight
+      F qa[2][S::KS];
+      if (j >= 2) aload<N>(a.Qring + (size_t)((k - j + 2) % win) * blk, r0 + c, rows, g, qa[0]);
+      // the increment is formed on its own and added to X once, so X (large
+      // next to one window's increment) is rounded once
+      mfma_acc_c<N>(dx, pa[t], bx, g, c);
+      mfma_acc_c<N>(pn, pa[t], bp, g, c);
 #pragma unroll
-        for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
-        dstore<N, F>(X, r0, rows, g, c, xa[t]);
+      for (int i = 0; i < MW - 1; ++i) {
+        if (i < j - 1) {
+          if (i + 1 < j - 1)
+            aload<N>(a.Qring + (size_t)((k - j + 3 + i) % win) * blk, r0 + c, rows, g,
+                     qa[(i + 1) & 1]);
+          mfma_acc_c<N>(dx, qa[i & 1], bx + (size_t)(i + 1) * 2 * N * N, g, c);
+          mfma_acc_c<N>(pn, qa[i & 1], bp + (size_t)(i + 1) * 2 * N * N, g, c);
+        }
       }
-      if (new_p) dstore<N, F>(Pout, r0, rows, g, c, pn);
+#pragma unroll
+      for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
+      dstore<N, F>(X, r0, rows, g, c, xa[t]);
+      dstore<N, F>(P, r0, rows, g, c, pn);
       if (s2 >= 0) fetch(s2, t);
     }
     s = s2;
-    buf ^= 1;
+    __syncthreads();  // every wave is done with this shift's coefficients
   }
 }
 
-// After the last iteration: every increment still pending (also one whose
-// deferring update has not been applied by a small step yet) is added, X^(s)
-// += P^(s)_prev Mxd^(s). One thread per complex entry of a row block.
+// After the last iteration: every update window still open (the solve ended
+// without its update applying it) is applied to X,
+//   X += P Cx + sum_{i < j-1} Q_{k-j+2+i} Ex_i
+// with the FP64 window state of the last update that ran (k = its iteration).
+// One thread per complex entry of a row block.
 template <typename F>
 __global__ __launch_bounds__(BMS_WG) void k_update_drain(UpdateArgs<F, F> a) {
   using CF = cplx<F>;
   const SolverFlags* fl = a.flags;
+  const int u = fl->upd_done;
+  if (u < 0 || fl->upd_stop) return;
+  const int slot = u & 1, k = u - 1, win = a.win;
   const int n = a.n, ns = a.ns;
-  const size_t blk = (size_t)a.rows * n;
+  const size_t blk = (size_t)a.rows * n, nn = (size_t)n * n;
+  const size_t fam = (size_t)BMS_MAX_WIN * nn;
   const size_t e = (size_t)blockIdx.x * BMS_WG + threadIdx.x;
   if (e >= blk) return;
   const size_t row = e / n;
-  const int j = (int)(e - row * n);
-  for (int s = 1; s < ns; ++s) {
-    int m = fl->upd_done != fl->pp_done[s] ? fl->pp_mode[s] : PP_NONE;
-    int pend = fl->pp_pend[s], cb = fl->pp_cur[s];
-    const CF* md = a.Mxd + (size_t)s * n * n;
-    if (m == PP_DEFER) {
-      pend = 1;
-      cb ^= 1;
-      md = a.Mx + (size_t)s * n * n;
-    } else if (m == PP_FLUSH) {
-      pend = 0;
-      cb ^= 1;
-    } else if (m == PP_DRAIN) {
-      pend = 0;
+  const int col = (int)(e - row * n);
+  for (int s = 0; s < ns; ++s) {
+    const int j = fl->win_j[slot][s];
+    if (j == 0 || fl->win_flush[slot][s]) continue;
+    const double2* xf = a.wst + (size_t)(slot * ns + s) * 2 * fam;
+    const CF* P = a.P + (size_t)s * blk + row * n;
+    double2 acc = make_double2(0, 0);
+    for (int kk = 0; kk < n; ++kk) acc = cfma(to_d(P[kk]), xf[(size_t)kk * n + col], acc);
+    for (int i = 0; i < j - 1; ++i) {
+      const CF* Q = a.Qring + (size_t)((k - j + 2 + i) % win) * blk + row * n;
+      const double2* ex = xf + (size_t)(i + 1) * nn;
+      for (int kk = 0; kk < n; ++kk) acc = cfma(to_d(Q[kk]), ex[(size_t)kk * n + col], acc);
     }
-    if (!pend) continue;
-    const CF* P = a.P + ((size_t)(cb ^ 1) * ns + s) * blk + row * n;
-    CF acc = czero<CF>();
-    for (int k = 0; k < n; ++k) acc = cfma(P[k], md[(size_t)k * n + j], acc);
     CF* X = a.X + (size_t)a.xidx[s] * blk + e;
-    *X = cadd(*X, acc);
+    *X = cadd(*X, from_d<CF>(acc));
   }
 }
 
@@ -416,6 +433,11 @@ hipError_t launch_mf(hipStream_t st, const UpdateArgs<F, F>& a) {
 }  // namespace
 
 bool update_mfma_supported(int n) { return n == 8 || n == 16; }
+
+template <typename F>
+int update_mfma_max_win() {
+  return MfWin<F>::MW;
+}
 
 // two_tiles: two 16-row tiles per wave instead of one
 template <typename F>
@@ -439,3 +461,5 @@ template hipError_t launch_update_mfma<double>(hipStream_t, const UpdateArgs<dou
 template hipError_t launch_update_mfma<float>(hipStream_t, const UpdateArgs<float, float>&, bool);
 template hipError_t launch_update_drain<double>(hipStream_t, const UpdateArgs<double, double>&);
 template hipError_t launch_update_drain<float>(hipStream_t, const UpdateArgs<float, float>&);
+template int update_mfma_max_win<double>();
+template int update_mfma_max_win<float>();
