@@ -138,16 +138,17 @@ int scratch_buf(bms_ctx* c, int slot, size_t bytes, void** p) {
 
 extern "C" int bms_destroy(bms_ctx* c) {
   if (!c) return BMS_EINVAL;
-  if (c->stream) hipStreamSynchronize(c->stream);
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->links64.p) hipFree(c->links64.p);
-  if (c->links32.p) hipFree(c->links32.p);
+  // teardown: a failing release cannot be reported past this point
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->links64.p) (void)hipFree(c->links64.p);
+  if (c->links32.p) (void)hipFree(c->links32.p);
   for (auto& b : c->scratch)
-    if (b.p) hipFree(b.p);
-  for (auto e : c->evpool) hipEventDestroy(e);
-  if (c->ev_in) hipEventDestroy(c->ev_in);
-  if (c->ev_out) hipEventDestroy(c->ev_out);
-  if (c->stream) hipStreamDestroy(c->stream);
+    if (b.p) (void)hipFree(b.p);
+  for (auto e : c->evpool) (void)hipEventDestroy(e);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return BMS_OK;
 }
