@@ -359,6 +359,51 @@ def write_traffic(workload, prec, fetch_csv, write_csv, cal_fetch_csv, cal_write
     return path
 
 
+def trace_gaps(path, split_ms=50.0):
+    """Idle time of the GPU inside the first solve of a rocprofv3 kernel trace
+    (--kernel-trace CSV): the dispatches are cut into bursts at host pauses
+    longer than split_ms; the first burst with update kernels is the solve.
+    Returns its span, the time some kernel ran (union of the intervals) and
+    the distribution of the gaps between one kernel's end and the next one's
+    start (launch latency, host checks between chunks, host work between
+    phases): what a persistent kernel could at most remove."""
+    import csv
+    ev = []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            ev.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]),
+                       row.get("Kernel_Name", "")))
+    ev.sort()
+    bursts, cur, last_end = [], [], None
+    for e in ev:
+        if cur and e[0] - last_end > split_ms * 1e6:
+            bursts.append(cur)
+            cur = []
+        cur.append(e)
+        last_end = e[1] if last_end is None or not cur[:-1] else max(last_end, e[1])
+    if cur:
+        bursts.append(cur)
+    solve = next(b for b in bursts if any("k_update" in e[2] for e in b))
+    busy, gaps, end = 0, [], None
+    for a, b, _ in solve:
+        if end is None or a >= end:
+            if end is not None:
+                gaps.append(a - end)
+            busy += b - a
+            end = b
+        elif b > end:
+            busy += b - end
+            end = b
+    span = solve[-1][1] - solve[0][0]
+    edges = [(0, 5e3), (5e3, 20e3), (20e3, 100e3), (100e3, 1e6), (1e6, 1e18)]
+    hist = {("%g-%g us" % (lo / 1e3, hi / 1e3) if hi < 1e18 else ">%g us" % (lo / 1e3)):
+            dict(count=sum(lo <= g < hi for g in gaps),
+                 ms=round(sum(g for g in gaps if lo <= g < hi) / 1e6, 2)) for lo, hi in edges}
+    return dict(kernels=len(solve), span_ms=round(span / 1e6, 2), busy_ms=round(busy / 1e6, 2),
+                idle_ms=round((span - busy) / 1e6, 2), idle_frac=round((span - busy) / span, 4),
+                mean_gap_us=round(sum(gaps) / max(1, len(gaps)) / 1e3, 2), gaps=hist)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,7 +447,13 @@ def main():
                     help="with --write-traffic: folder of the JSON file")
     ap.add_argument("--profile-command", default="",
                     help="with --write-traffic: the command the counter runs used ({} = counter)")
+    ap.add_argument("--trace-gaps", metavar="KERNEL_TRACE_CSV", default=None,
+                    help="print the GPU idle time inside the first solve of a rocprofv3 "
+                         "kernel trace of this benchmark; then exit (no GPU)")
     args = ap.parse_args()
+    if args.trace_gaps:
+        print(json.dumps(trace_gaps(args.trace_gaps)))
+        return
     if args.write_traffic:
         prec, fcsv, wcsv, cfcsv, cwcsv, run = args.write_traffic
         line = [l for l in open(run) if l.startswith("{")][-1]
