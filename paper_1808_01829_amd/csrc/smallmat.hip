@@ -70,6 +70,11 @@ __device__ void sm_identity(double2* A, int n) {
 // G = R^H R with R upper triangular and a real positive diagonal (so that
 // {Q, R} = qr(V) has Q = V R^-1 for G = V^H V). Returns 0, or BMS_EBREAKDOWN
 // when a pivot is <= tol * trace(G), or BMS_ENAN.
+// Right-looking in place: R starts as the upper triangle of G; step j takes
+// the square root of the pivot, scales row j, and subtracts row j's outer
+// product from the trailing rows. Every entry sees the same operations in
+// the same order as the dot-product (left-looking) form, so the factor is
+// the same bit for bit, with no one-thread loops between the barriers.
 __device__ int sm_chol_upper(double2* R, const double2* G, int n, double tol) {
   __shared__ int status;
   __shared__ double trace;
@@ -79,36 +84,39 @@ __device__ int sm_chol_upper(double2* R, const double2* G, int n, double tol) {
     for (int i = 0; i < n; ++i) tr += G[i * n + i].x;
     trace = tr;
   }
-  for (int e = threadIdx.x; e < n * n; e += BMS_WG) R[e] = make_double2(0, 0);
+  for (int e = threadIdx.x; e < n * n; e += BMS_WG) {
+    int i = e / n, l = e - (e / n) * n;
+    R[e] = l >= i ? G[e] : make_double2(0, 0);
+  }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     if (threadIdx.x == 0) {
-      double d = G[j * n + j].x;
-#pragma unroll 4
-      for (int k = 0; k < j; ++k) d -= cabs2(R[k * n + j]);
+      double d = R[j * n + j].x;
       if (!(d == d) || !(trace == trace) || !(fabs(trace) < 1e300)) status = BMS_ENAN;
       else if (!(d > tol * trace)) status = BMS_EBREAKDOWN;
       R[j * n + j] = make_double2(status ? 1.0 : sqrt(d), 0);
     }
     __syncthreads();
     if (status) return status;
-    double djj = R[j * n + j].x;
-    for (int i = j + 1 + threadIdx.x; i < n; i += BMS_WG) {
-      double2 s = G[j * n + i];
-#pragma unroll 4
-      for (int k = 0; k < j; ++k) s = csub(s, cmul(cconj(R[k * n + j]), R[k * n + i]));
-      R[j * n + i] = cdiv_real(s, djj);
+    const double djj = R[j * n + j].x;
+    for (int l = j + 1 + threadIdx.x; l < n; l += BMS_WG) R[j * n + l] = cdiv_real(R[j * n + l], djj);
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += BMS_WG) {
+      const int i = j + 1 + e / m, l = j + 1 + (e - (e / m) * m);
+      if (l >= i) R[i * n + l] = csub(R[i * n + l], cmul(cconj(R[j * n + i]), R[j * n + l]));
     }
     __syncthreads();
   }
   return 0;
 }
 
-// X = R^-1 for upper triangular R (one thread per column)
+// X = R^-1 for upper triangular R, one row of X per step (from the last),
+// the columns of a row in parallel
 __device__ void sm_triinv_upper(double2* X, const double2* R, int n) {
-  for (int j = threadIdx.x; j < n; j += BMS_WG) {
-    for (int i = n - 1; i >= 0; --i) {
-      if (i > j) {
+  for (int i = n - 1; i >= 0; --i) {
+    for (int j = threadIdx.x; j < n; j += BMS_WG) {
+      if (j < i) {
         X[i * n + j] = make_double2(0, 0);
         continue;
       }
@@ -117,8 +125,8 @@ __device__ void sm_triinv_upper(double2* X, const double2* R, int n) {
       for (int k = i + 1; k <= j; ++k) s = csub(s, cmul(R[i * n + k], X[k * n + j]));
       X[i * n + j] = cdiv_real(s, R[i * n + i].x);
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Ainv = A^-1 by Gauss-Jordan elimination with partial pivoting; A is
@@ -130,19 +138,26 @@ __device__ int sm_inv_general(double2* Ainv, double2* A, int n) {
   sm_identity(Ainv, n);
   if (threadIdx.x == 0) status = 0;
   for (int c = 0; c < n; ++c) {
-    if (threadIdx.x == 0) {
-      int p = c;
-      double best = cabs2(A[c * n + c]);
-#pragma unroll 4
-      for (int r = c + 1; r < n; ++r) {
-        double v = cabs2(A[r * n + c]);
-        if (v > best) {
-          best = v;
-          p = r;
+    // pivot: the first row r >= c of largest |A[r][c]| (the diagonal's own
+    // value decides a NaN there; NaN below it is never taken), by a
+    // reduction over the first wave
+    if (threadIdx.x < 64) {
+      const int r = c + (int)threadIdx.x;
+      double v = r < n ? cabs2(A[r * n + c]) : -1.0;
+      if (r > c && !(v == v)) v = -1.0;
+      int idx = r;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double v2 = __shfl_down(v, off);
+        const int i2 = __shfl_down(idx, off);
+        if (v2 > v || (v2 == v && i2 < idx)) {
+          v = v2;
+          idx = i2;
         }
       }
-      if (!(best > 0) || !(best < 1e300)) status = BMS_ENAN;
-      piv = p;
+      if (threadIdx.x == 0) {
+        if (!(v > 0) || !(v < 1e300)) status = BMS_ENAN;
+        piv = idx;
+      }
     }
     __syncthreads();
     if (status) return status;
