@@ -159,6 +159,8 @@ def per_vector(ctx, bms, m, r, Bd, tol, cols, torch):
 
 
 FP64_VALU_PEAK_TFLOPS = 78.6
+MFMA_F64_PEAK_TFLOPS = 78.6   # dense FP64 matrix cores
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix cores
 
 
 def action_measure(ctx, r, Bd, X, torch, reps=5):
@@ -556,6 +558,7 @@ def main():
     torch.cuda.synchronize()
     s_timed = time.perf_counter() - t0
     kt = ctx.timing_read()
+    kf = ctx.timing_flops()
     ctx.timing(False)
     log("bench: one instrumented solve (direct launches, events) %.3f s, %d iterations" % (
         s_timed, st_timed["iterations"]))
@@ -571,6 +574,20 @@ def main():
                     unit="GB/s", frac=round(dk["gbs"] / HBM_PEAK_GBS, 4),
                     traffic=stored_traffic(args.workload, prec, dom),
                     algorithmic_bytes_per_launch=round(dk["bytes"] / dk["launches"]))
+    # the same launches against the matrix cores: their time at the FP64 and
+    # FP32 MFMA peaks next to their time at the HBM peak (the larger bounds)
+    f64, f32 = kf.get(dom, (0.0, 0.0))
+    if f64 + f32 > 0:
+        t = dk["ms_total"] * 1e-3
+        t_mfma = f64 / (MFMA_F64_PEAK_TFLOPS * 1e12) + f32 / (MFMA_F32_PEAK_TFLOPS * 1e12)
+        t_hbm = dk["bytes"] / (HBM_PEAK_GBS * 1e9)
+        roofline["mfma"] = dict(
+            flops_f64_per_launch=round(f64 / dk["launches"]),
+            flops_f32_per_launch=round(f32 / dk["launches"]),
+            peaks_tflops=dict(f64=MFMA_F64_PEAK_TFLOPS, f32=MFMA_F32_PEAK_TFLOPS),
+            frac=round(t_mfma / t, 4),
+            note="time at the MFMA peaks / measured time; the HBM view above is %.4f" % (
+                t_hbm / t))
 
     action = action_measure(ctx, r, Bd, X, torch)
     log("bench: action %s" % action)

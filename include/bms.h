@@ -345,17 +345,21 @@ int bms_rhmc_trajectory(bms_ctx* ctx, const bms_rhmc_params* p, void* U, void* P
  *   BMS_KERNEL_HOP      half hop, links + in + out (+ aux for the D_eo hop)
  *   BMS_KERNEL_GRAM     the iteration's four Grams: P, Q, W read
  *   BMS_KERNEL_CHOLQR   Cholesky-QR Gram: Q, W read
- *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per active
- *                       shift P^(s), X^(s) read and written (variants 4, 5:
- *                       per shift other than the smallest, every second
- *                       iteration P^(s) read and written, and in the other
- *                       two directions, X^(s) read, X^(s) and P^(s) written)
+ *   BMS_KERNEL_UPDATE   fused update: Q, W read, Q written, and per shift
+ *                       whose update window it applies P^(s), X^(s) read and
+ *                       written plus, once, the earlier Q blocks the longest
+ *                       such window spans (every active shift every iteration
+ *                       for variants 0..3 and 6)
  *   BMS_KERNEL_SMALL    the n x n kernels (no block data)
  *   BMS_KERNEL_FORCE    the whole bms_force call (for variant 0 its D_oe hops
  *                       included): every solution read once, the 4V FP64
  *                       links once, the output written once
  * bms_timing_enable(ctx, 1) also clears the
  * accumulators; bms_timing_read returns them (host pointers, any may be NULL).
+ * bms_timing_flops returns the matrix-core work of the same launches for
+ * BMS_KERNEL_UPDATE (the real products of the Q step and of the applied
+ * windows, 2 flops per multiply-add, rows x (2n)^2 each), split into FP64 and
+ * FP32 arithmetic; 0 for the other classes and for the vector kernels.
  */
 #define BMS_KERNEL_HOP 0
 #define BMS_KERNEL_GRAM 1
@@ -370,10 +374,11 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
 /*
  * Kernel variant selection. For BMS_KERNEL_UPDATE: 4 and 5 = the
  * matrix-core (MFMA) kernel at n = 8 and 16 (FP32 or FP64 blocks, the Q step
- * in FP64) with one or two 16-row tiles per wave, where the solutions of the
- * shifts other than the smallest take two iterations' increments at once
- * (X^(s) += P^(s)_k-1 a^(s)_k-1 + P^(s)_k a^(s)_k, two direction buffers per
- * shift: 7 instead of 8 block vectors moved per shift every two iterations);
+ * in FP64) with one or two 16-row tiles per wave, where the shifts other
+ * than the smallest are updated once per window of iterations (4 in FP64,
+ * 8 in FP32: X^(s) and P^(s) of the whole window from the window's start and
+ * the Q blocks it spans, 4 block vectors per shift per window instead of per
+ * iteration; Algorithm 1's updates composed over the window);
  * 6 = the same kernel updating every shift every iteration, one tile per
  * wave; 0..3 = the vector kernels
  * (0 = four row chunks per work-group with both coefficient columns in
@@ -461,6 +466,7 @@ int bms_solve_batch(int nprob, bms_ctx* const* ctxs, const double* mass, const i
                     void* const* X, bms_stats* stats, int* status);
 int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,
                     double* bytes);
+int bms_timing_flops(const bms_ctx* ctx, int kernel, double* flops_f64, double* flops_f32);
 
 #ifdef __cplusplus
 }

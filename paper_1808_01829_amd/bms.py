@@ -47,7 +47,7 @@ EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create
            "bms_rational_apply", "bms_set_hop_config", "bms_get_hop_config",
            "bms_set_tune_cache", "bms_set_gauge_improved", "bms_gauge_action",
            "bms_gauge_force", "bms_gauge_update", "bms_kinetic_energy",
-           "bms_default_rhmc_params", "bms_rhmc_trajectory"]
+           "bms_default_rhmc_params", "bms_rhmc_trajectory", "bms_timing_flops"]
 
 
 class bms_opts(ctypes.Structure):
@@ -146,6 +146,7 @@ def _lib():
         L.bms_timing_enable.argtypes = [vp, i]
         L.bms_set_variant.argtypes = [vp, i, i]
         L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
+        L.bms_timing_flops.argtypes = [vp, i, dp, dp]
         L.bms_get_variant.argtypes = [vp, i, ip]
         L.bms_set_hop_config.argtypes = [vp, i, ip]
         L.bms_get_hop_config.argtypes = [vp, i, ip]
@@ -374,6 +375,13 @@ def bms_timing_read(ctx, kernel):
     return ms.value, nl.value, by.value
 
 
+def bms_timing_flops(ctx, kernel):
+    """Returns (FP64 flops, FP32 flops) of matrix-core work accumulated for a kernel class."""
+    f64, f32 = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, _lib().bms_timing_flops(ctx, int(kernel), ctypes.byref(f64), ctypes.byref(f32)))
+    return f64.value, f32.value
+
+
 class Context:
     """Owns a bms_ctx; torch-tensor convenience wrappers over the C calls."""
 
@@ -516,6 +524,9 @@ class Context:
 
     def timing_read(self):
         return {KERNEL_NAMES[k]: bms_timing_read(self.h, k) for k in range(len(KERNEL_NAMES))}
+
+    def timing_flops(self):
+        return {KERNEL_NAMES[k]: bms_timing_flops(self.h, k) for k in range(len(KERNEL_NAMES))}
 
     def force(self, alpha, X, flags=BMS_FORCE_RAW):
         import torch

@@ -245,6 +245,7 @@ extern "C" int bms_timing_enable(bms_ctx* c, int enable) {
     c->kt_ms[k] = 0;
     c->kt_launches[k] = 0;
     c->kt_bytes[k] = 0;
+    c->kt_flops64[k] = c->kt_flops32[k] = 0;
   }
   return BMS_OK;
 }
@@ -255,6 +256,14 @@ extern "C" int bms_timing_read(const bms_ctx* c, int kernel, double* ms, long lo
   if (ms) *ms = c->kt_ms[kernel];
   if (launches) *launches = c->kt_launches[kernel];
   if (bytes) *bytes = c->kt_bytes[kernel];
+  return BMS_OK;
+}
+
+extern "C" int bms_timing_flops(const bms_ctx* c, int kernel, double* flops_f64,
+                                double* flops_f32) {
+  if (!c || kernel < 0 || kernel >= BMS_NKERNELS) return BMS_EINVAL;
+  if (flops_f64) *flops_f64 = c->kt_flops64[kernel];
+  if (flops_f32) *flops_f32 = c->kt_flops32[kernel];
   return BMS_OK;
 }
 

@@ -119,6 +119,7 @@ struct bms_ctx {
   double kt_ms[BMS_NKERNELS] = {0};
   long long kt_launches[BMS_NKERNELS] = {0};
   double kt_bytes[BMS_NKERNELS] = {0};
+  double kt_flops64[BMS_NKERNELS] = {0}, kt_flops32[BMS_NKERNELS] = {0};
   std::vector<hipEvent_t> evpool;
   // graph cache for the iteration chunk
   hipGraphExec_t graph_exec = nullptr;

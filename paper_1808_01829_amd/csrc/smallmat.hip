@@ -347,7 +347,8 @@ __global__ __launch_bounds__(BMS_WG) void k_small_reliable(SmallParams p, SmallS
 
 // Completion of one iteration's small step: count this block's arrival and
 // whether its shift met tol; the last block to arrive stops the solve when
-// all did, logs the update's traffic and advances the iteration counter. The
+// all did, logs the update's traffic and work and advances the iteration
+// counter. The
 // update moves 3 block vectors for the Q step, 4 for each shift it applies
 // (P and X read and written) and, once, the ring buffers of the longest
 // window applied that are not in registers (Q_{k0+1} .. Q_{k-1}).
@@ -360,16 +361,19 @@ __device__ void finish_shift(const SmallParams& p, const SmallState& s, SolverFl
       __threadfence();
       if ((v >> 16) == p.ns || fl->error) fl->stop = 1;
       const int ws = (fl->iter + 1) & 1;
-      int units = 3, qx = 0;
+      int units = 3, qx = 0, prods = 0;
       for (int i = 0; i < p.ns; ++i) {
         const int j = fl->win_j[ws][i];
         if (j > 0 && (fl->win_flush[ws][i] || fl->stop)) {
           units += 4;
+          prods += 2 * j;
           qx = j - 2 > qx ? j - 2 : qx;
         }
       }
       units += qx;
-      if (s.upd_log && fl->iter < p.max_iter) s.upd_log[fl->iter] = units;
+      // block vectors moved, and the n x n right products of the applied
+      // windows above bit 16 (the Q step's two are added by the host)
+      if (s.upd_log && fl->iter < p.max_iter) s.upd_log[fl->iter] = units | (prods << 16);
       fl->need_explicit = 0;
       fl->iter = fl->iter + 1;
       atomicExch(s.counter, 0);

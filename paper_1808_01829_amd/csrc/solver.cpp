@@ -444,7 +444,15 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double S = (double)w.blk * sizeof(cplx<T>);
-    for (int k = 0; k < hf.iter; ++k) c->kt_bytes[BMS_KERNEL_UPDATE] += units[k] * S;
+    // a real product of a row block by a (2n x 2n) matrix: rows (2n)^2 FMA
+    const double prod = 2.0 * w.rows * (2.0 * n) * (2.0 * n);
+    const bool mf = update_mfma_supported(n) && (c->update_variant < 0 || c->update_variant >= 4);
+    for (int k = 0; k < hf.iter; ++k) {
+      c->kt_bytes[BMS_KERNEL_UPDATE] += (units[k] & 0xffff) * S;
+      if (!mf) continue;
+      c->kt_flops64[BMS_KERNEL_UPDATE] += 2 * prod;  // the Q step, FP64
+      (mixed ? c->kt_flops32 : c->kt_flops64)[BMS_KERNEL_UPDATE] += (units[k] >> 16) * prod;
+    }
   }
   if (mixed) {
     if ((rc = enqueue_reliable(c, w, sp, mass, B, Xout, xmap, R1, R2, R0, true))) return rc;
