@@ -559,6 +559,9 @@ def main():
     s_timed = time.perf_counter() - t0
     kt = ctx.timing_read()
     kf = ctx.timing_flops()
+    # per-launch bound of each class: each launch against whichever roof binds it
+    kfloor = {k: ctx.timing_floor(k, HBM_PEAK_GBS * 1e9, MFMA_F64_PEAK_TFLOPS * 1e12,
+                                  MFMA_F32_PEAK_TFLOPS * 1e12) for k in kt}
     ctx.timing(False)
     log("bench: one instrumented solve (direct launches, events) %.3f s, %d iterations" % (
         s_timed, st_timed["iterations"]))
@@ -588,6 +591,12 @@ def main():
             frac=round(t_mfma / t, 4),
             note="time at the MFMA peaks / measured time; the HBM view above is %.4f" % (
                 t_hbm / t))
+        # each launch against whichever roof binds it (the window-closing
+        # launches on the matrix cores, the others on HBM)
+        t_floor = kfloor[dom]
+        roofline["per_launch_bound"] = dict(
+            frac=round(t_floor / t, 4), floor_ms_per_launch=round(t_floor / dk["launches"] * 1e3, 4),
+            note="sum over launches of max(bytes / HBM peak, MFMA flops / MFMA peaks) / measured time")
 
     action = action_measure(ctx, r, Bd, X, torch)
     log("bench: action %s" % action)

@@ -358,8 +358,15 @@ int bms_rhmc_trajectory(bms_ctx* ctx, const bms_rhmc_params* p, void* U, void* P
  * accumulators; bms_timing_read returns them (host pointers, any may be NULL).
  * bms_timing_flops returns the matrix-core work of the same launches for
  * BMS_KERNEL_UPDATE (the real products of the Q step and of the applied
- * windows, 2 flops per multiply-add, rows x (2n)^2 each), split into FP64 and
- * FP32 arithmetic; 0 for the other classes and for the vector kernels.
+ * windows, 2 flops per multiply-add: per complex product 3 rows n^2 for
+ * n = 16, rows (2n)^2 for n = 8), split into FP64 and FP32 arithmetic; 0 for
+ * the other classes and for the vector kernels.
+ * bms_timing_floor returns in *seconds the least time the recorded launches
+ * of a class need at the given peaks (bytes/s, FP64 and FP32 flops/s, each
+ * > 0): for BMS_KERNEL_UPDATE the sum over its launches of
+ * max(bytes / hbm, flops_f64 / f64 + flops_f32 / f32), each launch bound by
+ * whichever roof is higher for it; for the other classes bytes / hbm.
+ * BMS_EINVAL for a bad kernel, a NULL output or a peak that is not positive.
  */
 #define BMS_KERNEL_HOP 0
 #define BMS_KERNEL_GRAM 1
@@ -467,6 +474,8 @@ int bms_solve_batch(int nprob, bms_ctx* const* ctxs, const double* mass, const i
 int bms_timing_read(const bms_ctx* ctx, int kernel, double* ms, long long* launches,
                     double* bytes);
 int bms_timing_flops(const bms_ctx* ctx, int kernel, double* flops_f64, double* flops_f32);
+int bms_timing_floor(const bms_ctx* ctx, int kernel, double hbm_bytes_per_s,
+                     double f64_flops_per_s, double f32_flops_per_s, double* seconds);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,8 @@ EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create
            "bms_rational_apply", "bms_set_hop_config", "bms_get_hop_config",
            "bms_set_tune_cache", "bms_set_gauge_improved", "bms_gauge_action",
            "bms_gauge_force", "bms_gauge_update", "bms_kinetic_energy",
-           "bms_default_rhmc_params", "bms_rhmc_trajectory", "bms_timing_flops"]
+           "bms_default_rhmc_params", "bms_rhmc_trajectory", "bms_timing_flops",
+           "bms_timing_floor"]
 
 
 class bms_opts(ctypes.Structure):
@@ -147,6 +148,7 @@ def _lib():
         L.bms_set_variant.argtypes = [vp, i, i]
         L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         L.bms_timing_flops.argtypes = [vp, i, dp, dp]
+        L.bms_timing_floor.argtypes = [vp, i, d, d, d, dp]
         L.bms_get_variant.argtypes = [vp, i, ip]
         L.bms_set_hop_config.argtypes = [vp, i, ip]
         L.bms_get_hop_config.argtypes = [vp, i, ip]
@@ -382,6 +384,15 @@ def bms_timing_flops(ctx, kernel):
     return f64.value, f32.value
 
 
+def bms_timing_floor(ctx, kernel, hbm_bytes_per_s, f64_flops_per_s, f32_flops_per_s):
+    """Least time (s) the recorded launches of a kernel class need at the given peaks."""
+    t = ctypes.c_double()
+    _check(ctx, _lib().bms_timing_floor(ctx, int(kernel), float(hbm_bytes_per_s),
+                                        float(f64_flops_per_s), float(f32_flops_per_s),
+                                        ctypes.byref(t)))
+    return t.value
+
+
 class Context:
     """Owns a bms_ctx; torch-tensor convenience wrappers over the C calls."""
 
@@ -527,6 +538,10 @@ class Context:
 
     def timing_flops(self):
         return {KERNEL_NAMES[k]: bms_timing_flops(self.h, k) for k in range(len(KERNEL_NAMES))}
+
+    def timing_floor(self, kernel, hbm_bytes_per_s, f64_flops_per_s, f32_flops_per_s):
+        k = KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else int(kernel)
+        return bms_timing_floor(self.h, k, hbm_bytes_per_s, f64_flops_per_s, f32_flops_per_s)
 
     def force(self, alpha, X, flags=BMS_FORCE_RAW):
         import torch

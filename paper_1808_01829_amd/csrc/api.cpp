@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "internal.h"
@@ -247,6 +248,7 @@ extern "C" int bms_timing_enable(bms_ctx* c, int enable) {
     c->kt_bytes[k] = 0;
     c->kt_flops64[k] = c->kt_flops32[k] = 0;
   }
+  c->kt_upd_launch.clear();
   return BMS_OK;
 }
 
@@ -264,6 +266,24 @@ extern "C" int bms_timing_flops(const bms_ctx* c, int kernel, double* flops_f64,
   if (!c || kernel < 0 || kernel >= BMS_NKERNELS) return BMS_EINVAL;
   if (flops_f64) *flops_f64 = c->kt_flops64[kernel];
   if (flops_f32) *flops_f32 = c->kt_flops32[kernel];
+  return BMS_OK;
+}
+
+extern "C" int bms_timing_floor(const bms_ctx* c, int kernel, double hbm_bytes_per_s,
+                                double f64_flops_per_s, double f32_flops_per_s,
+                                double* seconds) {
+  if (!c || kernel < 0 || kernel >= BMS_NKERNELS || !seconds || !(hbm_bytes_per_s > 0) ||
+      !(f64_flops_per_s > 0) || !(f32_flops_per_s > 0))
+    return BMS_EINVAL;
+  double t = 0;
+  if (kernel == BMS_KERNEL_UPDATE && !c->kt_upd_launch.empty()) {
+    const std::vector<double>& L = c->kt_upd_launch;
+    for (size_t i = 0; i + 2 < L.size(); i += 3)
+      t += std::max(L[i] / hbm_bytes_per_s, L[i + 1] / f64_flops_per_s + L[i + 2] / f32_flops_per_s);
+  } else {
+    t = c->kt_bytes[kernel] / hbm_bytes_per_s;
+  }
+  *seconds = t;
   return BMS_OK;
 }
 

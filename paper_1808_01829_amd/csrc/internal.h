@@ -120,6 +120,8 @@ struct bms_ctx {
   long long kt_launches[BMS_NKERNELS] = {0};
   double kt_bytes[BMS_NKERNELS] = {0};
   double kt_flops64[BMS_NKERNELS] = {0}, kt_flops32[BMS_NKERNELS] = {0};
+  // per update launch: algorithmic bytes, FP64 and FP32 matrix-core flops
+  std::vector<double> kt_upd_launch;
   std::vector<hipEvent_t> evpool;
   // graph cache for the iteration chunk
   hipGraphExec_t graph_exec = nullptr;

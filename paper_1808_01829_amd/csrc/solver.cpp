@@ -444,14 +444,24 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double S = (double)w.blk * sizeof(cplx<T>);
-    // a real product of a row block by a (2n x 2n) matrix: rows (2n)^2 FMA
-    const double prod = 2.0 * w.rows * (2.0 * n) * (2.0 * n);
+    // matrix-core flops of one complex right product of a row block by an
+    // n x n matrix: three real products (rows n^2 FMA each) for n = 16, one
+    // real product by the 2n x 2n form (rows (2n)^2 FMA) for n = 8
+    const double prod = n == 16 ? 6.0 * w.rows * n * n : 2.0 * w.rows * (2.0 * n) * (2.0 * n);
     const bool mf = update_mfma_supported(n) && (c->update_variant < 0 || c->update_variant >= 4);
     for (int k = 0; k < hf.iter; ++k) {
-      c->kt_bytes[BMS_KERNEL_UPDATE] += (units[k] & 0xffff) * S;
-      if (!mf) continue;
-      c->kt_flops64[BMS_KERNEL_UPDATE] += 2 * prod;  // the Q step, FP64
-      (mixed ? c->kt_flops32 : c->kt_flops64)[BMS_KERNEL_UPDATE] += (units[k] >> 16) * prod;
+      const double b = (units[k] & 0xffff) * S;
+      c->kt_bytes[BMS_KERNEL_UPDATE] += b;
+      double f64 = 0, f32 = 0;
+      if (mf) {
+        f64 = 2 * prod;  // the Q step, FP64
+        (mixed ? f32 : f64) += (units[k] >> 16) * prod;
+      }
+      c->kt_flops64[BMS_KERNEL_UPDATE] += f64;
+      c->kt_flops32[BMS_KERNEL_UPDATE] += f32;
+      c->kt_upd_launch.push_back(b);
+      c->kt_upd_launch.push_back(f64);
+      c->kt_upd_launch.push_back(f32);
     }
   }
   if (mixed) {

@@ -112,6 +112,38 @@ __device__ __forceinline__ void mfma_acc_c(typename Mf<F>::V (&d)[MfShape<N>::NT
     }
 }
 
+// n = 16: the complex right product by Gauss's three real products. With
+// the A operand of a lane holding complex columns 4g .. 4g+3 of its row (the
+// same contiguous run as above), k-step ks contracts over complex column
+// kc = 4g + ks, and the three accumulators gather
+//   d0 = sum Re a Re M,  d1 = sum Im a Im M,  d2 = sum (Re a + Im a)(Re M + Im M),
+// from which Re(a M) = d0 - d1 and Im(a M) = d2 - d0 - d1 (mfma3_re/_im).
+// Output column c of every accumulator is complex column c, so the two
+// results land in the layout of the n-tiles above (tile 0 real parts, tile 1
+// imaginary parts). 12 matrix-core steps per product and 16-row tile, against
+// 16 for the 32 x 32 real form. M: complex 16 x 16 in LDS, (re, im) pairs.
+template <typename F>
+__device__ __forceinline__ void mfma3(typename Mf<F>::V (&d)[3], const F (&a)[MfShape<16>::KS],
+                                      const F* M, int g, int c) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int e = 2 * ((4 * g + ks) * 16 + c);
+    const F mr = M[e], mi = M[e + 1];
+    const F ar = a[2 * ks], ai = a[2 * ks + 1];
+    d[0] = Mf<F>::mfma(ar, mr, d[0]);
+    d[1] = Mf<F>::mfma(ai, mi, d[1]);
+    d[2] = Mf<F>::mfma(ar + ai, mr + mi, d[2]);
+  }
+}
+template <typename V>
+__device__ __forceinline__ V mfma3_re(const V (&d)[3]) {
+  return d[0] - d[1];
+}
+template <typename V>
+__device__ __forceinline__ V mfma3_im(const V (&d)[3]) {
+  return d[2] - d[0] - d[1];
+}
+
 // A-operand reals of one tile row (row r, reals g*KS .. g*KS+KS-1) in the
 // arithmetic type F. Rows past the end read row 0 and are zeroed, with no
 // branch around the loads (so the loads of several tiles stay in flight).
@@ -204,7 +236,8 @@ struct MfWin {
 // first shift of a tile they come from L2.
 // One tile per wave: four waves per SIMD in FP32, three in FP64 (the register
 // count the compiler picks by itself leaves fewer; in FP64 four waves need
-// spills, whose scratch traffic reached HBM).
+// spills, whose scratch traffic reached HBM). For n = 16 every complex
+// product (Q step and shift windows) takes the three-product form.
 template <typename F, int N, int NTILE>
 __global__ __launch_bounds__(BMS_WG)
 __attribute__((amdgpu_waves_per_eu(NTILE == 1 ? (sizeof(F) == 4 ? 4 : 3) : 1)))
@@ -258,12 +291,36 @@ void k_update_mfma(UpdateArgs<F, F> a) {
     int i = e / N, j = e - (e / N) * N;
     double2 t = make_double2(0.0, 0.0);
     for (int kk = 0; kk < N; ++kk) t = cfma(cs[i * N + kk], cs[N * N + kk * N + j], t);
-    bput<N>(qb0, i, j, cs[N * N + e]);
-    bput<N>(qb1, i, j, make_double2(-t.x, -t.y));
+    if constexpr (N == 16) {
+      // complex matrices for the three-product form (qb0: rho^-1, then -alpha rho^-1)
+      qb0[2 * e] = cs[N * N + e].x;
+      qb0[2 * e + 1] = cs[N * N + e].y;
+      qb0[2 * N * N + 2 * e] = -t.x;
+      qb0[2 * N * N + 2 * e + 1] = -t.y;
+    } else {
+      bput<N>(qb0, i, j, cs[N * N + e]);
+      bput<N>(qb1, i, j, make_double2(-t.x, -t.y));
+    }
   }
   __syncthreads();
   dx4 qd[NTILE][S::NT];
-  {
+  if constexpr (N == 16) {
+    double av[NTILE][S::KS], wv[NTILE][S::KS];
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) {
+      const int r0 = (tile0 + t) * 16;
+      aload<N>(Qin, r0 + c, rows, g, av[t]);
+      aload<N>(a.W, r0 + c, rows, g, wv[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) {
+      dx4 d3[3] = {dx4{0.0, 0.0, 0.0, 0.0}, dx4{0.0, 0.0, 0.0, 0.0}, dx4{0.0, 0.0, 0.0, 0.0}};
+      mfma3<double>(d3, av[t], qb0, g, c);
+      mfma3<double>(d3, wv[t], qb0 + 2 * N * N, g, c);
+      qd[t][0] = mfma3_re(d3);
+      qd[t][1] = mfma3_im(d3);
+    }
+  } else {
     double b0[S::KS][S::NT], b1[S::KS][S::NT];
     double av[NTILE][S::KS], wv[NTILE][S::KS];
 #pragma unroll
@@ -315,14 +372,16 @@ void k_update_mfma(UpdateArgs<F, F> a) {
     __syncthreads();  // the shift coefficients overwrite this LDS
   }
 
-  // the P and X tiles of a shift (the next shift's are loaded while the
-  // current one finishes)
+  // the P and X tiles of a shift (the next shift's P, and for n = 8 its X,
+  // are loaded while the current one finishes; for n = 16 X is loaded after
+  // the products, which keeps the three-accumulator form at three waves per
+  // SIMD with 16 bytes of spills outside the product loop)
   F pa[NTILE][S::KS];
   VF xa[NTILE][S::NT];
   auto fetch = [&](int s, int t) {
     const int r0 = (tile0 + t) * 16;
     aload<N>(a.P + (size_t)s * blk, r0 + c, rows, g, pa[t]);
-    dload<N, F>(a.X + (size_t)a.xidx[s] * blk, r0, rows, g, c, xa[t]);
+    if constexpr (N != 16) dload<N, F>(a.X + (size_t)a.xidx[s] * blk, r0, rows, g, c, xa[t]);
   };
   int s = mask ? __ffsll((long long)mask) - 1 : -1;
   if (s >= 0) {
@@ -351,10 +410,11 @@ void k_update_mfma(UpdateArgs<F, F> a) {
 #pragma unroll
     for (int t = 0; t < NTILE; ++t) {
       const int r0 = (tile0 + t) * 16;
-      VF pn[S::NT], dx[S::NT];
+      constexpr int NACC = N == 16 ? 3 : S::NT;  // accumulators of one product family
+      VF pn[NACC], dx[NACC];
 #pragma unroll
-      for (int nt = 0; nt < S::NT; ++nt) {
-        pn[nt] = qn[t][nt];
+      for (int nt = 0; nt < NACC; ++nt) {
+        pn[nt] = (N == 16 || nt >= S::NT) ? VF{0, 0, 0, 0} : qn[t][nt];
         dx[nt] = VF{0, 0, 0, 0};
       }
       // ring buffers Q_{k-j+2} .. Q_k, two in flight
@@ -362,22 +422,38 @@ void k_update_mfma(UpdateArgs<F, F> a) {
       if (j >= 2) aload<N>(a.Qring + (size_t)((k - j + 2) % win) * blk, r0 + c, rows, g, qa[0]);
       // the increment is formed on its own and added to X once, so X (large
       // next to one window's increment) is rounded once
-      mfma_acc_c<N>(dx, pa[t], bx, g, c);
-      mfma_acc_c<N>(pn, pa[t], bp, g, c);
+      auto prod = [&](const F(&av)[S::KS], int m) {
+        if constexpr (N == 16) {
+          mfma3<F>(dx, av, bx + (size_t)m * 2 * N * N, g, c);
+          mfma3<F>(pn, av, bp + (size_t)m * 2 * N * N, g, c);
+        } else {
+          mfma_acc_c<N>(dx, av, bx + (size_t)m * 2 * N * N, g, c);
+          mfma_acc_c<N>(pn, av, bp + (size_t)m * 2 * N * N, g, c);
+        }
+      };
+      prod(pa[t], 0);
 #pragma unroll
       for (int i = 0; i < MW - 1; ++i) {
         if (i < j - 1) {
           if (i + 1 < j - 1)
             aload<N>(a.Qring + (size_t)((k - j + 3 + i) % win) * blk, r0 + c, rows, g,
                      qa[(i + 1) & 1]);
-          mfma_acc_c<N>(dx, qa[i & 1], bx + (size_t)(i + 1) * 2 * N * N, g, c);
-          mfma_acc_c<N>(pn, qa[i & 1], bp + (size_t)(i + 1) * 2 * N * N, g, c);
+          prod(qa[i & 1], i + 1);
         }
       }
+      if constexpr (N == 16) {
+        dload<N, F>(X, r0, rows, g, c, xa[t]);
+        xa[t][0] += mfma3_re(dx);
+        xa[t][1] += mfma3_im(dx);
+        const VF pst[S::NT] = {qn[t][0] + mfma3_re(pn), qn[t][1] + mfma3_im(pn)};
+        dstore<N, F>(X, r0, rows, g, c, xa[t]);
+        dstore<N, F>(P, r0, rows, g, c, pst);
+      } else {
 #pragma unroll
-      for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
-      dstore<N, F>(X, r0, rows, g, c, xa[t]);
-      dstore<N, F>(P, r0, rows, g, c, pn);
+        for (int nt = 0; nt < S::NT; ++nt) xa[t][nt] += dx[nt];
+        dstore<N, F>(X, r0, rows, g, c, xa[t]);
+        dstore<N, F>(P, r0, rows, g, c, pn);
+      }
       if (s2 >= 0) fetch(s2, t);
     }
     s = s2;

@@ -68,6 +68,11 @@ int main(void) {
   EXPECT(bms_timing_read(ctx, BMS_KERNEL_HOP, &ms, &nl, &by) == BMS_OK);
   EXPECT(ms == 0.0 && nl == 0 && by == 0.0);
   EXPECT(bms_timing_read(ctx, 99, NULL, NULL, NULL) == BMS_EINVAL);
+  double fl = -1;
+  EXPECT(bms_timing_floor(ctx, BMS_KERNEL_UPDATE, 8e12, 78.6e12, 157.3e12, &fl) == BMS_OK);
+  EXPECT(fl == 0.0);
+  EXPECT(bms_timing_floor(ctx, BMS_KERNEL_UPDATE, -1.0, 1.0, 1.0, &fl) == BMS_EINVAL);
+  EXPECT(bms_timing_floor(ctx, BMS_KERNEL_UPDATE, 1.0, 1.0, 1.0, NULL) == BMS_EINVAL);
   EXPECT(bms_set_variant(ctx, BMS_KERNEL_UPDATE, 4) == BMS_OK);
   int v = -5;
   EXPECT(bms_get_variant(ctx, BMS_KERNEL_UPDATE, &v) == BMS_OK && v == 4);

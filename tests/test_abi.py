@@ -119,6 +119,14 @@ def test_calls_without_gauge_fail_on_the_host(lib):
                                    ctypes.byref(by)) == bms.BMS_OK
         assert (ms.value, nl.value, by.value) == (0.0, 0, 0.0)
         assert lib.bms_timing_read(ctx, 99, None, None, None) == bms.BMS_EINVAL
+        fl = ctypes.c_double(-1)
+        assert lib.bms_timing_floor(ctx, bms.BMS_KERNEL_UPDATE, 8e12, 78.6e12, 157.3e12,
+                                    ctypes.byref(fl)) == bms.BMS_OK
+        assert fl.value == 0.0
+        assert lib.bms_timing_floor(ctx, bms.BMS_KERNEL_UPDATE, 0.0, 1.0, 1.0,
+                                    ctypes.byref(fl)) == bms.BMS_EINVAL
+        assert lib.bms_timing_floor(ctx, 99, 1.0, 1.0, 1.0, ctypes.byref(fl)) == bms.BMS_EINVAL
+        assert lib.bms_timing_floor(ctx, 0, 1.0, 1.0, 1.0, None) == bms.BMS_EINVAL
         assert lib.bms_set_variant(ctx, bms.BMS_KERNEL_UPDATE, 1) == bms.BMS_OK
     finally:
         assert lib.bms_destroy(ctx) == bms.BMS_OK

@@ -48,6 +48,11 @@ def test_graph_replay_matches_direct_launches(torch, prec):
                 # every block iteration of every phase is timed: two half hops each
                 assert kt["hop"][1] == 2 * st["iterations"]
                 assert kt["hop"][0] > 0 and kt["update"][0] > 0
+                # each update launch bound by the higher of its two roofs:
+                # positive, at least the bytes-only bound, below the measured time
+                fl = ctx.timing_floor("update", 8e12, 78.6e12, 157.3e12)
+                assert kt["update"][2] / 8e12 <= fl * (1 + 1e-12)
+                assert 0 < fl < kt["update"][0] * 1e-3
             _ = (Bd * 2).sum().item()  # eager work between replays
             res.setdefault((g, tm), []).append((to_np(X), st["iterations"]))
         ctx.timing(False)
