@@ -260,7 +260,8 @@ def operator_block_gain(bms, torch, dims, Ud, reps=5):
                 e1.record()
                 torch.cuda.synchronize()
                 t[n] = e0.elapsed_time(e1) * 1e3 / reps
-            algo = vh * nl * 9 * 2 * b + 2 * vh * 3 * 16 * 2 * b
+            epl = 6 if ctx.link_rows() == 2 else 9  # link entries read (two-row SU(3) links: 6)
+            algo = vh * nl * epl * 2 * b + 2 * vh * 3 * 16 * 2 * b
             res["f64" if b == 8 else "f32"] = dict(
                 us_n16=round(t[16], 1), us_n1=round(t[1], 1),
                 gbs_n16=round(algo / (t[16] * 1e-6) / 1e9, 1),
@@ -430,6 +431,8 @@ def main():
                          "(median, min, max reported aside)")
     ap.add_argument("--no-force", action="store_true",
                     help="skip the force-kernel measurement (reported aside)")
+    ap.add_argument("--link-rows", type=int, default=2, choices=(2, 3),
+                    help="rows of each SU(3) link the hop reads (2: third row rebuilt)")
     ap.add_argument("--no-rhmc", action="store_true",
                     help="skip the RHMC trajectory measurement (reported aside)")
     ap.add_argument("--no-operators", action="store_true",
@@ -507,7 +510,9 @@ def main():
     Ud = torch.from_numpy(U).to(dev)
     Bd = torch.from_numpy(B).to(dev)
     ctx = bms.Context(dims, (1, 1, 1, -1))
+    ctx.set_link_rows(args.link_rows)
     ctx.set_gauge(Ud)
+    link_rows = ctx.link_rows()
     opts = bms.bms_default_opts()
     opts.precision = bms.BMS_PREC_F64 if prec == "f64" else bms.BMS_PREC_MIXED
     if w.get("reliable"):
@@ -705,7 +710,7 @@ def main():
         cpu_baseline=cpu,
         cpu_baseline_1thread=cpu1,
         rhs_shift_solves_per_s=round(value * r.n_poles, 3),
-        dslash=dict(kernel="hop (both half hops)",
+        dslash=dict(kernel="hop (both half hops)", link_rows=link_rows,
                     gbs=round(kernels["hop"]["gbs"], 1) if "hop" in kernels else None,
                     hbm_frac=round(kernels["hop"]["gbs"] / HBM_PEAK_GBS, 4)
                     if "hop" in kernels else None),

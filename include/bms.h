@@ -140,8 +140,27 @@ int bms_destroy(bms_ctx* ctx);
  * half hop needs, with the 1/2, eta_mu and boundary factors folded in (and
  * the backward links daggered), in FP64 and FP32. U is not referenced after
  * the call returns (the copy is ordered on the stream).
+ * With two link rows selected (bms_set_link_rows, the default) the call also
+ * keeps the first two rows of every link and checks that each third row is
+ * what SU(3) implies, row2 = conj(row0 x row1) for the unscaled matrix, to
+ * 1e-12 in every part; when all pass, the half hop reads two rows per link
+ * and rebuilds the third (a third fewer link bytes), else it reads all
+ * nine entries. That check waits for the import (a host synchronisation).
  */
 int bms_set_gauge(bms_ctx* ctx, const void* U);
+
+/*
+ * How many rows of each SU(3) link the half hop reads: 2 (default: when the
+ * field loaded by bms_set_gauge passes its check) or 3 (always all nine
+ * entries). Takes effect at the next bms_set_gauge; BMS_EINVAL for other
+ * values. bms_get_link_rows returns in *rows the form the current links are
+ * read in: 2, or 3 (also for the improved operator's links, which are not
+ * SU(3) matrices), and in *max_dev (may be NULL) the largest difference the
+ * last check found between a third row and the SU(3) one (+inf for a value
+ * that is not finite; -1 when no check ran).
+ */
+int bms_set_link_rows(bms_ctx* ctx, int rows);
+int bms_get_link_rows(const bms_ctx* ctx, int* rows, double* max_dev);
 
 /*
  * Load the links of the improved, less local staggered operator (the
@@ -433,7 +452,7 @@ int bms_get_hop_config(const bms_ctx* ctx, int precision, int cfg[5]);
  * Cache file of bms_autotune (a text file of JSON lines, one per tuned
  * problem shape; NULL or "" = no cache). With a cache set, bms_autotune
  * first looks for the key (device architecture, lattice, n, n_shifts,
- * precision) and applies the stored choice without timing anything; on a
+ * precision, links per site and link rows read) and applies the stored choice without timing anything; on a
  * miss it times the candidates and appends the result.
  */
 int bms_set_tune_cache(bms_ctx* ctx, const char* path);

@@ -48,7 +48,7 @@ EXPORTS = ["bms_default_opts", "bms_error_string", "bms_last_error", "bms_create
            "bms_set_tune_cache", "bms_set_gauge_improved", "bms_gauge_action",
            "bms_gauge_force", "bms_gauge_update", "bms_kinetic_energy",
            "bms_default_rhmc_params", "bms_rhmc_trajectory", "bms_timing_flops",
-           "bms_timing_floor"]
+           "bms_timing_floor", "bms_set_link_rows", "bms_get_link_rows"]
 
 
 class bms_opts(ctypes.Structure):
@@ -149,6 +149,8 @@ def _lib():
         L.bms_timing_read.argtypes = [vp, i, dp, ctypes.POINTER(ctypes.c_longlong), dp]
         L.bms_timing_flops.argtypes = [vp, i, dp, dp]
         L.bms_timing_floor.argtypes = [vp, i, d, d, d, dp]
+        L.bms_set_link_rows.argtypes = [vp, i]
+        L.bms_get_link_rows.argtypes = [vp, ip, dp]
         L.bms_get_variant.argtypes = [vp, i, ip]
         L.bms_set_hop_config.argtypes = [vp, i, ip]
         L.bms_get_hop_config.argtypes = [vp, i, ip]
@@ -421,6 +423,18 @@ class Context:
         import torch
         assert U.dtype == torch.complex128 and tuple(U.shape) == (4, self.vol, 3, 3)
         bms_set_gauge(self.h, U)
+
+    def set_link_rows(self, rows):
+        """2: the hop reads SU(3) links as two rows when the field allows (default); 3: all nine
+        entries. Takes effect at the next set_gauge."""
+        _check(self.h, _lib().bms_set_link_rows(self.h, int(rows)))
+
+    def link_rows(self, with_deviation=False):
+        """Rows per link the current links are read in (2 or 3); with_deviation: also the
+        largest third-row deviation from SU(3) the last check found (-1: none ran)."""
+        r, d = ctypes.c_int(), ctypes.c_double()
+        _check(self.h, _lib().bms_get_link_rows(self.h, ctypes.byref(r), ctypes.byref(d)))
+        return (r.value, d.value) if with_deviation else r.value
 
     def gauge_action(self, beta, U):
         S = ctypes.c_double()

@@ -144,6 +144,8 @@ extern "C" int bms_destroy(bms_ctx* c) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->links64.p) (void)hipFree(c->links64.p);
   if (c->links32.p) (void)hipFree(c->links32.p);
+  for (DevBuf* b : {&c->links64r, &c->links32r, &c->lsign, &c->lcheck})
+    if (b->p) (void)hipFree(b->p);
   for (auto& b : c->scratch)
     if (b.p) (void)hipFree(b.p);
   for (auto e : c->evpool) (void)hipEventDestroy(e);
@@ -165,10 +167,49 @@ extern "C" int bms_set_gauge(bms_ctx* c, const void* U) {
   // padding sites of the last block are never read; zero them once
   HIP_TRY(c, launch_fill_zero(c->stream, c->links64.p, nlink * sizeof(double2)));
   HIP_TRY(c, launch_fill_zero(c->stream, c->links32.p, nlink * sizeof(float2)));
-  HIP_TRY(c, launch_gauge_import(c, U, c->links64.p, c->links32.p));
+  const bool two = c->link_rows == 2;
+  if (two) {
+    const size_t nrow = (size_t)2 * c->nblk * 48 << c->sbl;
+    if ((rc = ensure_buf(c, c->links64r, nrow * sizeof(double2)))) return rc;
+    if ((rc = ensure_buf(c, c->links32r, nrow * sizeof(float2)))) return rc;
+    if ((rc = ensure_buf(c, c->lsign, (size_t)2 * c->vh * sizeof(uint32_t)))) return rc;
+    if ((rc = ensure_buf(c, c->lcheck, 256))) return rc;
+    HIP_TRY(c, launch_fill_zero(c->stream, c->links64r.p, nrow * sizeof(double2)));
+    HIP_TRY(c, launch_fill_zero(c->stream, c->links32r.p, nrow * sizeof(float2)));
+    HIP_TRY(c, launch_fill_zero(c->stream, c->lcheck.p, 16));
+  }
+  HIP_TRY(c, launch_gauge_import(c, U, c->links64.p, c->links32.p, two ? c->links64r.p : nullptr,
+                                 two ? c->links32r.p : nullptr, two ? c->lsign.p : nullptr,
+                                 two ? c->lcheck.p : nullptr));
+  c->links_two_rows = false;
+  c->link_dev = -1;
+  if (two) {
+    // the hop reads two rows only if every third row is the SU(3) one to 1e-12
+    unsigned long long bits = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, c->lcheck.p, sizeof bits, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double dev;
+    memcpy(&dev, &bits, sizeof dev);
+    c->link_dev = dev;
+    c->links_two_rows = dev <= 1e-12;
+  }
   c->nlinks = 8;
   c->gauge_set = true;
   return stream_end(c);
+}
+
+extern "C" int bms_set_link_rows(bms_ctx* c, int rows) {
+  if (!c) return BMS_EINVAL;
+  if (rows != 2 && rows != 3) return set_err(c, BMS_EINVAL, "link rows must be 2 or 3");
+  c->link_rows = rows;
+  return BMS_OK;
+}
+
+extern "C" int bms_get_link_rows(const bms_ctx* c, int* rows, double* max_dev) {
+  if (!c || !rows) return BMS_EINVAL;
+  *rows = c->links_two_rows && c->nlinks == 8 ? 2 : 3;
+  if (max_dev) *max_dev = c->nlinks == 8 ? c->link_dev : -1;
+  return BMS_OK;
 }
 
 extern "C" int bms_set_gauge_improved(bms_ctx* c, const void* V, const void* W) {
@@ -185,6 +226,8 @@ extern "C" int bms_set_gauge_improved(bms_ctx* c, const void* V, const void* W) 
   HIP_TRY(c, launch_fill_zero(c->stream, c->links64.p, nlink * sizeof(double2)));
   HIP_TRY(c, launch_fill_zero(c->stream, c->links32.p, nlink * sizeof(float2)));
   HIP_TRY(c, launch_gauge_import_improved(c, V, W, c->links64.p, c->links32.p));
+  c->links_two_rows = false;
+  c->link_dev = -1;
   c->nlinks = 16;
   c->gauge_set = true;
   return stream_end(c);

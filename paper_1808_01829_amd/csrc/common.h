@@ -156,7 +156,9 @@ __device__ __forceinline__ int neighbour_cb(int s, const SiteCoord& c, const Geo
 // link k (0..3 forward mu=k, 4..7 backward mu=k-4; for the improved operator
 // also 8..11 three-hop forward, 12..15 three-hop backward) element e (0..8,
 // row-major) of checkerboard site s lives at
-// ((s>>sbl)*per + k*9 + e) << sbl | (s & (SB-1)), per = 9 * links per site.
-__device__ __forceinline__ size_t link_off(uint32_t s, int k, int e, int sbl, int per = 72) {
-  return ((((size_t)(s >> sbl)) * per + k * 9 + e) << sbl) | (s & ((1u << sbl) - 1));
+// ((s>>sbl)*per + k*epl + e) << sbl | (s & (SB-1)), per = epl * links per
+// site, with epl = 9 entries per link, or 6 for links kept as two rows.
+__device__ __forceinline__ size_t link_off(uint32_t s, int k, int e, int sbl, int per = 72,
+                                           int epl = 9) {
+  return ((((size_t)(s >> sbl)) * per + k * epl + e) << sbl) | (s & ((1u << sbl) - 1));
 }

@@ -140,9 +140,12 @@ std::string tune_key(bms_ctx* c, int n, int ns, int precision) {
     size_t colon = arch.find(':');
     if (colon != std::string::npos) arch.resize(colon);
   }
+  // links per site and rows read per link: the hop's traffic, and so its
+  // best traversal, depend on them
+  const int rows = c->links_two_rows && c->nlinks == 8 ? 2 : 3;
   char buf[256];
-  snprintf(buf, sizeof buf, "%s|%d,%d,%d,%d|%d|%d|%d", arch.c_str(), c->dims[0], c->dims[1],
-           c->dims[2], c->dims[3], n, ns, precision);
+  snprintf(buf, sizeof buf, "%s|%d,%d,%d,%d|%d|%d|%d|L%dr%d", arch.c_str(), c->dims[0], c->dims[1],
+           c->dims[2], c->dims[3], n, ns, precision, c->nlinks, rows);
   return buf;
 }
 

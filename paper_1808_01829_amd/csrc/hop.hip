@@ -14,45 +14,78 @@ struct Bc {
 //   k = mu     :  +1/2 eta_mu(x) bf U_mu(x)              (hop to x+mu)
 //   k = 4 + mu :  -1/2 eta_mu(x) bb U_mu(x-mu)^dag       (hop to x-mu)
 // bf / bb = bc[mu] if that hop crosses the boundary. FP64 and FP32 copies.
-__global__ __launch_bounds__(BMS_WG) void k_gauge_import(const double2* __restrict__ U,
-                                                         double2* __restrict__ l64,
-                                                         float2* __restrict__ l32, Geom g, Bc bc,
-                                                         int sbl, int nblk, int vol) {
+// With r64 set, also the two-row copies (entries 0..5 of each link, FP64 and
+// FP32), bit k of sign[p][s] set when link k's scale c (+-1/2) is negative,
+// and in *dev the largest difference, over the links and the parts of their
+// entries, between a third row and the one the first two give for an SU(3)
+// matrix, row2(c V) = conj(row0 x row1) / c (+inf if not finite). A
+// non-negative double orders like its bit pattern, so an integer atomic
+// maximum of the bits keeps it.
+__device__ __forceinline__ void store_link(const double2 (&v)[9], double f, uint32_t s, int k,
+                                           size_t pbase, size_t rbase, int sbl, double2* l64,
+                                           float2* l32, double2* r64, float2* r32,
+                                           unsigned long long* dev, uint32_t& mask) {
+  for (int e = 0; e < 9; ++e) {
+    const size_t o = pbase + link_off(s, k, e, sbl);
+    l64[o] = v[e];
+    l32[o] = make_float2((float)v[e].x, (float)v[e].y);
+  }
+  if (!r64) return;
+  for (int e = 0; e < 6; ++e) {
+    const size_t o = rbase + link_off(s, k, e, sbl, 48, 6);
+    r64[o] = v[e];
+    r32[o] = make_float2((float)v[e].x, (float)v[e].y);
+  }
+  if (f < 0) mask |= 1u << k;
+  const double inv = 1.0 / f;
+  double d = 0;
+  for (int b = 0; b < 3; ++b) {
+    const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+    const double2 x = csub(cmul(v[b1], v[3 + b2]), cmul(v[b2], v[3 + b1]));
+    const double2 r = cscale(cconj(x), inv);
+    const double dx = fabs(r.x - v[6 + b].x), dy = fabs(r.y - v[6 + b].y);
+    d = dx > d ? dx : d;
+    d = dy > d ? dy : d;
+    if (!(dx == dx) || !(dy == dy)) d = __builtin_huge_val();
+  }
+  if (d > 0) atomicMax(dev, (unsigned long long)__double_as_longlong(d));
+}
+
+__global__ __launch_bounds__(BMS_WG) void k_gauge_import(
+    const double2* __restrict__ U, double2* __restrict__ l64, float2* __restrict__ l32,
+    double2* __restrict__ r64, float2* __restrict__ r32, uint32_t* __restrict__ sign,
+    unsigned long long* __restrict__ dev, Geom g, Bc bc, int sbl, int nblk, int vol) {
   uint32_t tid = blockIdx.x * BMS_WG + threadIdx.x;
   if (tid >= 2u * (uint32_t)g.vh) return;
   int par = tid >= (uint32_t)g.vh;
   uint32_t s = tid - (par ? g.vh : 0);
   SiteCoord c = site_coords(s, g, par);
   int co[4] = {c.x, c.y, c.z, c.t};
-  size_t pbase = (size_t)par * nblk * 72 << sbl;
+  const size_t pbase = (size_t)par * nblk * 72 << sbl;
+  const size_t rbase = (size_t)par * nblk * 48 << sbl;
   auto lex = [&](const int* q) { return q[0] + g.L[0] * (q[1] + g.L[1] * (q[2] + g.L[2] * q[3])); };
   int idx = lex(co);
+  uint32_t mask = 0;
   for (int mu = 0; mu < 4; ++mu) {
     int esum = 0;
     for (int nu = 0; nu < mu; ++nu) esum += co[nu];
     double eta = (esum & 1) ? -0.5 : 0.5;
+    double2 v[9];
     // forward
-    double ff = eta * ((co[mu] == g.L[mu] - 1) ? bc.b[mu] : 1);
+    const double ff = eta * ((co[mu] == g.L[mu] - 1) ? bc.b[mu] : 1);
     const double2* uf = U + ((size_t)mu * vol + idx) * 9;
-    for (int e = 0; e < 9; ++e) {
-      double2 v = cscale(uf[e], ff);
-      size_t o = pbase + link_off(s, mu, e, sbl);
-      l64[o] = v;
-      l32[o] = make_float2((float)v.x, (float)v.y);
-    }
+    for (int e = 0; e < 9; ++e) v[e] = cscale(uf[e], ff);
+    store_link(v, ff, s, mu, pbase, rbase, sbl, l64, l32, r64, r32, dev, mask);
     // backward: daggered link of the neighbour x - mu
     int nb[4] = {co[0], co[1], co[2], co[3]};
     nb[mu] = co[mu] == 0 ? g.L[mu] - 1 : co[mu] - 1;
-    double fb = -eta * ((co[mu] == 0) ? bc.b[mu] : 1);
+    const double fb = -eta * ((co[mu] == 0) ? bc.b[mu] : 1);
     const double2* ub = U + ((size_t)mu * vol + lex(nb)) * 9;
     for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        double2 v = cscale(cconj(ub[3 * b + a]), fb);
-        size_t o = pbase + link_off(s, 4 + mu, 3 * a + b, sbl);
-        l64[o] = v;
-        l32[o] = make_float2((float)v.x, (float)v.y);
-      }
+      for (int b = 0; b < 3; ++b) v[3 * a + b] = cscale(cconj(ub[3 * b + a]), fb);
+    store_link(v, fb, s, 4 + mu, pbase, rbase, sbl, l64, l32, r64, r32, dev, mask);
   }
+  if (sign) sign[(size_t)par * g.vh + s] = mask;
 }
 
 // Signed distance of hop k: one step forward (0..3) and back (4..7), for the
@@ -130,6 +163,19 @@ __device__ __forceinline__ float2 link_ld(const float2* p) {
   return make_float2(v.x, v.y);
 }
 
+// Third row of a link kept as two rows: row2 = conj(row0 x row1) / c with the
+// link's scale c = +-1/2 (neg: bit k of the site's sign mask).
+template <typename C>
+__device__ __forceinline__ void link_row2(C (&l)[9], bool neg) {
+  using T = decltype(C().x);
+  const T f = neg ? (T)-2 : (T)2;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+    l[6 + b] = cscale(cconj(csub(cmul(l[b1], l[3 + b2]), cmul(l[b2], l[3 + b1]))), f);
+  }
+}
+
 // Tiled traversal. A tile is hx x ty x tz x tt checkerboard sites (whole
 // x-rows); the tiles of one (y, z) pencil are walked along t. Work-groups go
 // to the 8 XCDs in turn (work-group b to XCD b % 8); XCD x takes pencils x,
@@ -172,13 +218,16 @@ __device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom
 // neighbouring columns) and a wave touches as few cache lines as the bytes
 // allow. In FP32 a thread's R columns are consecutive instead (g*R .. g*R+R-1),
 // which the compiler loads as 16-byte vectors.
-template <typename T, int R, bool NT, int NL>
+// EPL: link entries stored, 9, or 6 for SU(3) links kept as two rows (the
+// third rebuilt from them and the site's sign mask `sgn`).
+template <typename T, int R, bool NT, int NL, int EPL>
 __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ links,
                                                 const cplx<T>* __restrict__ in,
                                                 cplx<T>* __restrict__ out,
                                                 const cplx<T>* __restrict__ aux, T a, T b, Geom g,
                                                 int n, FastDiv dgrp, int par, int sbl,
-                                                const int* __restrict__ skip, HopTiles tiles) {
+                                                const int* __restrict__ skip, HopTiles tiles,
+                                                const uint32_t* __restrict__ sgn) {
   using C = cplx<T>;
   if (skip && *skip) return;
   const uint32_t ngrp = dgrp.d;  // n / R column groups per site
@@ -204,21 +253,23 @@ __global__ __launch_bounds__(BMS_WG) void k_hop(const cplx<T>* __restrict__ link
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
   const size_t st = (size_t)1 << sbl;
+  const uint32_t msk = EPL == 6 ? sgn[s] : 0u;
 #pragma unroll 2
   for (int k = 0; k < NL; ++k) {
     int mu = k & 3;
     int nb = neighbour_cb((int)s, c, g, mu, hop_dist(k));
     const C* src = in + (size_t)nb * 3 * n + j0;
-    const C* L = links + link_off(s, k, 0, sbl, 9 * NL);
+    const C* L = links + link_off(s, k, 0, sbl, EPL * NL, EPL);
     C l[9], v[3][R];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) l[e] = link_ld<NT>(L + e * st);
+    for (int e = 0; e < EPL; ++e) l[e] = link_ld<NT>(L + e * st);
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
       for (int r = 0; r < R; ++r) v[cb][r] = src[cb * n + r * cstep];
     // all of the hop's loads in flight before the first use (as in k_hop_q)
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (EPL == 6) link_row2(l, (msk >> k) & 1);
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
@@ -257,13 +308,16 @@ __device__ __forceinline__ double quad_bcast(double v) {
 // element e reaches the other three threads of the quad by a DPP broadcast
 // from lane e % 4. Columns as in k_hop (interleaved in FP64, consecutive in
 // FP32).
-template <typename T, int R, bool NT, int NL>
+// With links kept as two rows (EPL = 6) thread q loads entries q and 4 + q%2,
+// and every thread rebuilds the third row.
+template <typename T, int R, bool NT, int NL, int EPL>
 __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ links,
                                                   const cplx<T>* __restrict__ in,
                                                   cplx<T>* __restrict__ out,
                                                   const cplx<T>* __restrict__ aux, T a, T b,
                                                   Geom g, int n, int par, int sbl,
-                                                  const int* __restrict__ skip, HopTiles tiles) {
+                                                  const int* __restrict__ skip, HopTiles tiles,
+                                                  const uint32_t* __restrict__ sgn) {
   using C = cplx<T>;
   if (skip && *skip) return;
   // whole quads leave together (4 * Vh threads), so every DPP source lane is active
@@ -274,7 +328,11 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
   constexpr bool kInterleave = sizeof(T) == 8;
   const int cstep = kInterleave ? 4 : 1;
   const int j0 = kInterleave ? q : q * R;
-  const int e2 = q == 0 ? 8 : q + 4;  // thread 0 also fetches element 8 (others repeat q+4)
+  // second and third entries this thread fetches: 9 entries, q + 4 and
+  // (thread 0) 8, others repeat q + 4; 6 entries, 4 + q%2
+  const int e1 = EPL == 6 ? 4 + (q & 1) : q + 4;
+  const int e2 = q == 0 ? 8 : q + 4;
+  const uint32_t msk = EPL == 6 ? sgn[s] : 0u;
   SiteCoord c = site_coords(s, g, par);
   C acc[3][R];
 #pragma unroll
@@ -290,9 +348,9 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
     const int mu = k & 3;
     const int nb = neighbour_cb((int)s, c, g, mu, hop_dist(k));
     const C* src = in + (size_t)nb * 3 * n + j0;
-    const C* L = links + link_off(s, k, 0, sbl, 9 * NL);
-    const C t0 = link_ld<NT>(L + q * st), t1 = link_ld<NT>(L + (q + 4) * st),
-            t2 = link_ld<NT>(L + e2 * st);
+    const C* L = links + link_off(s, k, 0, sbl, EPL * NL, EPL);
+    const C t0 = link_ld<NT>(L + q * st), t1 = link_ld<NT>(L + e1 * st);
+    const C t2 = EPL == 9 ? link_ld<NT>(L + e2 * st) : t1;
     C v[3][R];
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb)
@@ -301,7 +359,7 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
     __builtin_amdgcn_sched_barrier(0);
     C l[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
+    for (int e = 0; e < EPL; ++e) {
       const C own = e < 4 ? t0 : (e < 8 ? t1 : t2);
       switch (e & 3) {
         case 0: l[e].x = quad_bcast<0>(own.x); l[e].y = quad_bcast<0>(own.y); break;
@@ -310,6 +368,7 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
         default: l[e].x = quad_bcast<3>(own.x); l[e].y = quad_bcast<3>(own.y);
       }
     }
+    if constexpr (EPL == 6) link_row2(l, (msk >> k) & 1);
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb)
 #pragma unroll
@@ -329,12 +388,14 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
 
 }  // namespace
 
-hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32) {
+hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32,
+                               void* r64, void* r32, void* sign, void* dev) {
   Bc bc;
   for (int i = 0; i < 4; ++i) bc.b[i] = c->bc[i];
   uint32_t nthr = 2u * c->vh;
   k_gauge_import<<<(nthr + BMS_WG - 1) / BMS_WG, BMS_WG, 0, c->stream>>>(
-      (const double2*)U, (double2*)l64, (float2*)l32, c->geom, bc, c->sbl, c->nblk, (int)c->vol);
+      (const double2*)U, (double2*)l64, (float2*)l32, (double2*)r64, (float2*)r32,
+      (uint32_t*)sign, (unsigned long long*)dev, c->geom, bc, c->sbl, c->nblk, (int)c->vol);
   return hipGetLastError();
 }
 
@@ -411,9 +472,13 @@ HopPlan hop_plan(const bms_ctx* c, int n, bool fp64) {
 template <typename T>
 hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* out, const void* aux,
                       double a, double b, const int* skip) {
-  const DevBuf& lb = sizeof(T) == 8 ? c->links64 : c->links32;
-  size_t pstride = (size_t)c->nblk * 9 * c->nlinks << c->sbl;
+  // SU(3) links as two rows when the field passed the import's check
+  const bool two = c->links_two_rows && c->nlinks == 8;
+  const DevBuf& lb = two ? (sizeof(T) == 8 ? c->links64r : c->links32r)
+                         : (sizeof(T) == 8 ? c->links64 : c->links32);
+  size_t pstride = (size_t)c->nblk * (two ? 6 : 9) * c->nlinks << c->sbl;
   const cplx<T>* links = (const cplx<T>*)lb.p + (size_t)par * pstride;
+  const uint32_t* sgn = two ? (const uint32_t*)c->lsign.p + (size_t)par * c->vh : nullptr;
   // Variants: 0 one thread per (site, column group), 1 four threads per site
   // sharing the links (n = 4, 8, 16, 32), 2 and 3 the same in the tiled
   // traversal; the default is 1, tiled in FP64 at n >= 16. The traversal's
@@ -424,20 +489,25 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   if (hp.quad) {
     dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);
     HopTiles tiles = hp.tiled ? hop_tiles(c, BMS_WG / 4, hp.ty, hp.tz, hp.tt) : HopTiles{};
-#define HOPQ(RR, NT, NL)                                                                   \
-  k_hop_q<T, RR, NT, NL><<<qgrid, BMS_WG, lds, c->stream>>>(                               \
+#define HOPQ(RR, NT, NL, EPL)                                                              \
+  k_hop_q<T, RR, NT, NL, EPL><<<qgrid, BMS_WG, lds, c->stream>>>(                          \
       links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom,  \
-      n, par, c->sbl, skip, tiles)
+      n, par, c->sbl, skip, tiles, sgn)
 #define HOPQN(RR)                                   \
   if (c->nlinks == 16) {                            \
     if (hp.nt)                                      \
-      HOPQ(RR, true, 16);                           \
+      HOPQ(RR, true, 16, 9);                        \
     else                                            \
-      HOPQ(RR, false, 16);                          \
+      HOPQ(RR, false, 16, 9);                       \
+  } else if (two) {                                 \
+    if (hp.nt)                                      \
+      HOPQ(RR, true, 8, 6);                         \
+    else                                            \
+      HOPQ(RR, false, 8, 6);                        \
   } else if (hp.nt)                                 \
-    HOPQ(RR, true, 8);                              \
+    HOPQ(RR, true, 8, 9);                           \
   else                                              \
-    HOPQ(RR, false, 8)
+    HOPQ(RR, false, 8, 9)
     switch (n) {
       case 4: HOPQN(1); break;
       case 8: HOPQN(2); break;
@@ -456,20 +526,25 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   HopTiles tiles = hp.tiled && BMS_WG % ngrp == 0
                        ? hop_tiles(c, BMS_WG / (int)ngrp, hp.ty, hp.tz, hp.tt)
                        : HopTiles{};
-#define HOP_LAUNCH(RR, NT, NL)                                                             \
-  k_hop<T, RR, NT, NL><<<grid, BMS_WG, lds, c->stream>>>(                                  \
+#define HOP_LAUNCH(RR, NT, NL, EPL)                                                        \
+  k_hop<T, RR, NT, NL, EPL><<<grid, BMS_WG, lds, c->stream>>>(                             \
       links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom,  \
-      n, dg, par, c->sbl, skip, tiles)
+      n, dg, par, c->sbl, skip, tiles, sgn)
 #define HOPN(RR)                                    \
   if (c->nlinks == 16) {                            \
     if (hp.nt)                                      \
-      HOP_LAUNCH(RR, true, 16);                     \
+      HOP_LAUNCH(RR, true, 16, 9);                  \
     else                                            \
-      HOP_LAUNCH(RR, false, 16);                    \
+      HOP_LAUNCH(RR, false, 16, 9);                 \
+  } else if (two) {                                 \
+    if (hp.nt)                                      \
+      HOP_LAUNCH(RR, true, 8, 6);                   \
+    else                                            \
+      HOP_LAUNCH(RR, false, 8, 6);                  \
   } else if (hp.nt)                                 \
-    HOP_LAUNCH(RR, true, 8);                        \
+    HOP_LAUNCH(RR, true, 8, 9);                     \
   else                                              \
-    HOP_LAUNCH(RR, false, 8)
+    HOP_LAUNCH(RR, false, 8, 9)
   if (R == 4)
     HOPN(4);
   else if (R == 2)

@@ -105,6 +105,14 @@ struct bms_ctx {
   bool gauge_set = false;
   int nlinks = 8;  // links per site and output parity: 8, or 16 with three-hop links
   DevBuf links64, links32;  // [parity][blocked links] complex
+  // The half hop's SU(3) links as their first two rows ([parity][blocked],
+  // six entries per link) and per site a mask of the links whose scale
+  // (+-1/2 times the phases) is negative; used when link_rows is 2 and every
+  // link of the field passed the check at import (links_two_rows).
+  DevBuf links64r, links32r, lsign, lcheck;
+  int link_rows = 2;            // bms_set_link_rows: 2 (when the field allows) or 3
+  bool links_two_rows = false;  // the hop reads links64r / links32r
+  double link_dev = -1;         // largest third-row deviation found (-1: not checked)
   std::vector<DevBuf> scratch;  // named by slot index
   std::string last_error;
   // kernel variants (bms_set_variant); -1 = built-in default
@@ -160,7 +168,8 @@ int link_update_dev(bms_ctx* c, double eps, const void* P, void* U);
 int kinetic_dev(bms_ctx* c, const void* P, double* K);
 
 // ---- launchers (all enqueue on c->stream) ---------------------------------
-hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32);
+hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32,
+                               void* r64, void* r32, void* sign, void* dev);
 // the improved operator: one-hop links V and three-hop links W (16 per site)
 hipError_t launch_gauge_import_improved(const bms_ctx* c, const void* V, const void* W, void* l64,
                                         void* l32);

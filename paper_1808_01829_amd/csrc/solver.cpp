@@ -276,8 +276,10 @@ std::string chunk_key(const bms_ctx* c, const Work& w, const SmallParams& sp, do
     SmallState sm;
   } k;
   memset(&k, 0, sizeof k);
+  const bool two = c->links_two_rows && c->nlinks == 8;
   const void* ptrs[16] = {w.W1, w.W, w.Q, w.P, w.X, w.Mx, w.Mp, w.flags, w.partials, w.sm.counter,
-                          c->links64.p, c->links32.p, w.Wm, w.sm.wst, nullptr, nullptr};
+                          two ? c->links64r.p : c->links64.p, two ? c->links32r.p : c->links32.p,
+                          w.Wm, w.sm.wst, two ? c->lsign.p : nullptr, nullptr};
   for (int i = 0; i < 16; ++i) k.p[i] = ptrs[i];
   k.mass = mass;
   k.K = K;
@@ -404,7 +406,9 @@ int solve_core(bms_ctx* c, double mass, int n, int ns, const double* sigma, cons
     HIP_TRY(c, hipMemcpyAsync(&hf, w.flags, sizeof hf, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->timing) {
-      double G = 9.0 * c->nlinks * c->vol * sizeof(T);
+      // links read by one half hop: nine entries, or six for two-row links
+      const int epl = c->links_two_rows && c->nlinks == 8 ? 6 : 9;
+      double G = (double)epl * c->nlinks * c->vol * sizeof(T);
       double S = (double)w.blk * sizeof(cplx<T>);
       // the explicit Cholesky-QR Gram (slot 4) normally exits at once: no bytes
       const double kbytes[7] = {G + 2 * S, G + 3 * S, 3 * S, 0, 0, 0, 0};

@@ -73,6 +73,12 @@ int main(void) {
   EXPECT(fl == 0.0);
   EXPECT(bms_timing_floor(ctx, BMS_KERNEL_UPDATE, -1.0, 1.0, 1.0, &fl) == BMS_EINVAL);
   EXPECT(bms_timing_floor(ctx, BMS_KERNEL_UPDATE, 1.0, 1.0, 1.0, NULL) == BMS_EINVAL);
+  int rows = 0;
+  double dev = 0;
+  EXPECT(bms_get_link_rows(ctx, &rows, &dev) == BMS_OK && rows == 3 && dev == -1.0);
+  EXPECT(bms_get_link_rows(ctx, &rows, NULL) == BMS_OK);
+  EXPECT(bms_set_link_rows(ctx, 1) == BMS_EINVAL);
+  EXPECT(bms_set_link_rows(ctx, 3) == BMS_OK && bms_set_link_rows(ctx, 2) == BMS_OK);
   EXPECT(bms_set_variant(ctx, BMS_KERNEL_UPDATE, 4) == BMS_OK);
   int v = -5;
   EXPECT(bms_get_variant(ctx, BMS_KERNEL_UPDATE, &v) == BMS_OK && v == 4);

@@ -127,6 +127,14 @@ def test_calls_without_gauge_fail_on_the_host(lib):
                                     ctypes.byref(fl)) == bms.BMS_EINVAL
         assert lib.bms_timing_floor(ctx, 99, 1.0, 1.0, 1.0, ctypes.byref(fl)) == bms.BMS_EINVAL
         assert lib.bms_timing_floor(ctx, 0, 1.0, 1.0, 1.0, None) == bms.BMS_EINVAL
+        rows = ctypes.c_int(0)
+        dev = ctypes.c_double(0)
+        assert lib.bms_get_link_rows(ctx, ctypes.byref(rows), ctypes.byref(dev)) == bms.BMS_OK
+        assert rows.value == 3 and dev.value == -1.0
+        assert lib.bms_get_link_rows(ctx, None, None) == bms.BMS_EINVAL
+        assert lib.bms_set_link_rows(ctx, 4) == bms.BMS_EINVAL
+        assert lib.bms_set_link_rows(ctx, 3) == bms.BMS_OK
+        assert lib.bms_set_link_rows(ctx, 2) == bms.BMS_OK
         assert lib.bms_set_variant(ctx, bms.BMS_KERNEL_UPDATE, 1) == bms.BMS_OK
     finally:
         assert lib.bms_destroy(ctx) == bms.BMS_OK

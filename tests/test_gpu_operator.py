@@ -127,3 +127,51 @@ def test_hop_tiled_traversal(torch, n):
         ref = O.mdagm(dims, bc, U, 0.05, 0.3, v)
         out = to_np(c.apply_mdagm(0.05, 0.3, to_dev(torch, v)))
         assert rel(out, ref) < 1e-13, variant
+
+
+@pytest.mark.parametrize("dims,n", [((4, 4, 4, 4), 16), ((4, 6, 2, 8), 3), ((8, 4, 4, 6), 8)])
+def test_hop_link_rows(torch, dims, n):
+    """The hop reads SU(3) links as two rows and rebuilds the third: the same
+    result as with all nine entries, both equal to the oracle; a field that is
+    not SU(3) (one link off by 1e-9, or every link scaled) is read in full."""
+    from paper_1808_01829_amd import bms
+    bc = (1, 1, 1, -1)
+    U = random_gauge(dims, 0.7, 105)
+    v = gaussian_block(dims, n, 106)
+    vd = to_dev(torch, v)
+    c = _ctx(dims, bc, U)
+    rows, dev = c.link_rows(with_deviation=True)
+    print("link rows", rows, "third-row deviation", dev)
+    assert rows == 2 and 0 <= dev <= 1e-14
+    two = {}
+    for par in (0, 1):
+        ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], axis=-1)
+        for variant in (-1, 0):
+            c.set_variant(bms.BMS_KERNEL_HOP, variant)
+            two[par, variant] = to_np(c.apply_hop(par, vd))
+            assert rel(two[par, variant], ref) < 1e-13
+            out32 = to_np(c.apply_hop(par, to_dev(torch, v.astype(np.complex64)), bms.BMS_PREC_F32))
+            assert rel(out32, ref) < 2e-6
+    c.set_variant(bms.BMS_KERNEL_HOP, -1)
+    c.set_link_rows(3)
+    c.set_gauge(to_dev(torch, U))
+    assert c.link_rows() == 3
+    for par in (0, 1):
+        assert rel(to_np(c.apply_hop(par, vd)), two[par, -1]) < 1e-14
+    with pytest.raises(bms.BmsError):
+        c.set_link_rows(4)
+    # fields the check turns away: one link perturbed, every link scaled
+    c.set_link_rows(2)
+    U1 = U.copy()
+    U1[2, 5, 1, 2] += 1e-9
+    U2 = U * 1.0001
+    for Ub, lo in ((U1, 1e-10), (U2, 1e-5)):
+        c.set_gauge(to_dev(torch, Ub))
+        rows, dev = c.link_rows(with_deviation=True)
+        assert rows == 3 and dev > lo
+        for par in (0, 1):
+            ref = np.stack([O.dslash_half(dims, bc, Ub, par, v[..., j]) for j in range(n)], axis=-1)
+            assert rel(to_np(c.apply_hop(par, vd)), ref) < 1e-13
+    c.set_gauge(to_dev(torch, U))
+    assert c.link_rows() == 2
+    c.close()
