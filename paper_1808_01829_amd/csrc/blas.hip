@@ -637,9 +637,11 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4(int rows, int n, int per_block
 }
 
 // ---- the four Grams of one iteration on the matrix cores --------------------
-// Real Gram tiles R = sum_rows x^T y (v_mfma_f64_16x16x4, 4 rows per step;
-// the lane holding row l/16, column l%16 of a 16-column tile serves as either
-// operand), FP64 accumulation for FP32 and FP64 inputs.
+// Real Gram tiles R = sum_rows x^T y (4 rows per step; the lane holding row
+// l/16, column l%16 of a 16-column tile serves as either operand), FP64
+// accumulation for FP32 and FP64 inputs: v_mfma_f64_16x16x4 on FP64 blocks;
+// on FP32 blocks v_mfma_f32_16x16x4 over one round of D steps (4D rows per
+// wave), whose FP32 tiles are then added into FP64 totals.
 //  n = 16: tile 0 holds the real parts of the 16 complex columns and tile 1 the
 //          imaginary parts, so each lane loads one whole complex per block and
 //          step; G[i][j] = R00[i][j] + R11[i][j] + i (R01[i][j] - R10[i][j]).
@@ -648,6 +650,7 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4(int rows, int n, int per_block
 // W^H W and Q^H Q are symmetric in real form: only tiles a <= b are summed.
 // D steps of 4 rows are in flight per wave (a register ring).
 typedef double gdx4 __attribute__((ext_vector_type(4)));
+typedef float gfx4 __attribute__((ext_vector_type(4)));
 
 template <typename T, int N>
 struct GramRow {
@@ -691,14 +694,16 @@ struct GramRaw {
     else
       return ((const T*)X)[r * 2 * N + c];
   }
-  // the step's operand values, zero for a row past the range
+  // the step's operand values (A: double, or float for FP32 blocks), zero
+  // for a row past the range
+  template <typename A>
   __device__ static __forceinline__ void use(const type& z, bool ok,
-                                             double (&v)[GramRow<T, N>::NT]) {
+                                             A (&v)[GramRow<T, N>::NT]) {
     if constexpr (N == 16) {
-      v[0] = ok ? (double)z.x : 0.0;
-      v[1] = ok ? (double)z.y : 0.0;
+      v[0] = ok ? (A)z.x : (A)0;
+      v[1] = ok ? (A)z.y : (A)0;
     } else {
-      v[0] = ok ? (double)z : 0.0;
+      v[0] = ok ? (A)z : (A)0;
     }
   }
 };
@@ -757,43 +762,98 @@ __global__ __launch_bounds__(BMS_WG) void k_gram4_mfma(int rows,
 #pragma unroll
   for (int u = 0; u < D; ++u) fetch(u, p[u], q[u], w[u]);
   __builtin_amdgcn_sched_barrier(0);
-  for (int st0 = 0; st0 < nst; st0 += D) {
+  if constexpr (sizeof(T) == 8) {
+    for (int st0 = 0; st0 < nst; st0 += D) {
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      const int st = st0 + u;
-      const bool ok = rbase + rstride * st < (size_t)rows;
-      double pc[NT], qc[NT], wc[NT];
-      RW::use(p[u], ok, pc);
-      RW::use(q[u], ok, qc);
-      RW::use(w[u], ok, wc);
-      fetch(st + D, p[u], q[u], w[u]);
-      // keep the refill here, D steps ahead of its use
-      __builtin_amdgcn_sched_barrier(0);
+      for (int u = 0; u < D; ++u) {
+        const int st = st0 + u;
+        const bool ok = rbase + rstride * st < (size_t)rows;
+        double pc[NT], qc[NT], wc[NT];
+        RW::use(p[u], ok, pc);
+        RW::use(q[u], ok, qc);
+        RW::use(w[u], ok, wc);
+        fetch(st + D, p[u], q[u], w[u]);
+        // keep the refill here, D steps ahead of its use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = 0; b < NT; ++b) {
+            apw[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pc[a], wc[b], apw[a][b], 0, 0, 0);
+            aqw[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(qc[a], wc[b], aqw[a][b], 0, 0, 0);
+          }
+        int e = 0;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = a; b < NT; ++b, ++e) {
+            aww[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[a], wc[b], aww[e], 0, 0, 0);
+            aqq[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(qc[a], qc[b], aqq[e], 0, 0, 0);
+          }
+      }
+    }
+  } else {
+    // FP32 products over one round, then into the FP64 totals
+    for (int st0 = 0; st0 < nst; st0 += D) {
+      gfx4 fpw[NT][NT], fqw[NT][NT], fww[NPAIR], fqq[NPAIR];
 #pragma unroll
       for (int a = 0; a < NT; ++a)
 #pragma unroll
-        for (int b = 0; b < NT; ++b) {
-          apw[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pc[a], wc[b], apw[a][b], 0, 0, 0);
-          aqw[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(qc[a], wc[b], aqw[a][b], 0, 0, 0);
-        }
-      int e = 0;
+        for (int b = 0; b < NT; ++b) fpw[a][b] = fqw[a][b] = gfx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int a = 0; a < NT; ++a)
+      for (int e = 0; e < NPAIR; ++e) fww[e] = fqq[e] = gfx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int b = a; b < NT; ++b, ++e) {
-          aww[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[a], wc[b], aww[e], 0, 0, 0);
-          aqq[e] = __builtin_amdgcn_mfma_f64_16x16x4f64(qc[a], qc[b], aqq[e], 0, 0, 0);
+      for (int u = 0; u < D; ++u) {
+        const int st = st0 + u;
+        const bool ok = rbase + rstride * st < (size_t)rows;
+        float pc[NT], qc[NT], wc[NT];
+        RW::use(p[u], ok, pc);
+        RW::use(q[u], ok, qc);
+        RW::use(w[u], ok, wc);
+        fetch(st + D, p[u], q[u], w[u]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = 0; b < NT; ++b) {
+            fpw[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(pc[a], wc[b], fpw[a][b], 0, 0, 0);
+            fqw[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(qc[a], wc[b], fqw[a][b], 0, 0, 0);
+          }
+        int e = 0;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = a; b < NT; ++b, ++e) {
+            fww[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(wc[a], wc[b], fww[e], 0, 0, 0);
+            fqq[e] = __builtin_amdgcn_mfma_f32_16x16x4f32(qc[a], qc[b], fqq[e], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = 0; b < NT; ++b) {
+            apw[a][b][k] += (double)fpw[a][b][k];
+            aqw[a][b][k] += (double)fqw[a][b][k];
+          }
+#pragma unroll
+        for (int e = 0; e < NPAIR; ++e) {
+          aww[e][k] += (double)fww[e][k];
+          aqq[e][k] += (double)fqq[e][k];
         }
+      }
     }
   }
   // one product at a time: every wave writes its real Gram (accumulator
-  // element k of lane (g, c) is tile row g + 4k, column c), then the block
-  // sums the four and forms the complex entries of its partial
+  // element k of lane (g, c) is tile row g + 4k for the f64 products, 4g + k
+  // for the f32 ones, column c), then the block sums the four and forms the
+  // complex entries of its partial
   double* R = red[wave];
   auto put = [&](int a, int b, const gdx4& d, bool mirror) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      int i = a * 16 + g + 4 * k, j = b * 16 + c;
+      int i = a * 16 + (sizeof(T) == 8 ? g + 4 * k : 4 * g + k), j = b * 16 + c;
       R[i * NR + j] = d[k];
       if (mirror) R[j * NR + i] = d[k];
     }

@@ -120,7 +120,9 @@ def test_two_iteration_update_matches_every_iteration(torch, n, max_iter):
 
 @pytest.mark.parametrize("n", [8, 16])
 def test_mfma_gram_mixed_precision_solve(torch, n):
-    """FP32 inputs to the MFMA Gram (FP64 accumulation) in the mixed solver."""
+    """FP32 blocks in the MFMA Gram (FP32 matrix-core products over rounds of 4D rows, FP64
+    totals) against the vector Gram (FP64 accumulation) in the mixed solver: every shift
+    converges and the iteration counts agree."""
     from paper_1808_01829_amd import bms
     dims = (6, 4, 4, 6)
     r = configs.workload_coefficients("c2")
