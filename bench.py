@@ -229,6 +229,44 @@ def force_measure(bms, torch, np, configs, reps=3):
                 hops_then_per_link_us=round(res[0][0], 1))
 
 
+def shard_local(bms, torch, dims, eps, n, reps=10):
+    """One GPU's share of the lattice split over 8 GPUs along t (the local
+    sub-lattice with its own periodic wrap standing in for the halo): the two
+    half hops at n columns in FP64 and FP32, their time and algorithmic GB/s
+    (two-row links when the field passes the check), and the bytes of one
+    t-face of the other parity that a half hop would exchange per
+    neighbour."""
+    from paper_1808_01829_amd.inputs import gaussian_block, random_gauge
+    L = list(dims)
+    L[3] = dims[3] // 8
+    vh = L[0] * L[1] * L[2] * L[3] // 2
+    ctx = bms.Context(L, (1, 1, 1, -1))
+    ctx.set_gauge(torch.from_numpy(random_gauge(L, eps, 7101)).cuda())
+    epl = 6 if ctx.link_rows() == 2 else 9
+    v = torch.from_numpy(gaussian_block(L, n, 7102)).cuda()
+    out = dict(lattice=L, n=n, link_rows=ctx.link_rows())
+    for prec, name, b in ((bms.BMS_PREC_F64, "f64", 8), (bms.BMS_PREC_F32, "f32", 4)):
+        x = v if b == 8 else v.to(torch.complex64)
+        for par in (1, 0):
+            ctx.apply_hop(par, x, prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            y = ctx.apply_hop(1, x, prec)
+            ctx.apply_hop(0, y, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps / 2
+        algo = vh * 8 * epl * 2 * b + 2 * vh * 3 * n * 2 * b
+        face = L[0] * L[1] * L[2] // 2 * 3 * n * 2 * b
+        out[name] = dict(us_per_hop=round(us, 1), gbs=round(algo / (us * 1e-6) / 1e9, 1),
+                         face_bytes=face)
+    ctx.close()
+    return out
+
+
 def operator_block_gain(bms, torch, dims, Ud, reps=5):
     """Half hops on one GPU for the unimproved operator (8 links per site)
     and the improved one (one-hop plus three-hop links, 16 per site; V = 9/8 U,
@@ -665,9 +703,13 @@ def main():
         log("bench: seeds %s" % (seeds,))
 
     operators = None
+    shard = None
     if not args.no_operators:
         operators = operator_block_gain(bms, torch, dims, Ud)
         log("bench: operators %s" % (operators,))
+        if dims[3] % 16 == 0:
+            shard = shard_local(bms, torch, dims, w["eps"], n)
+            log("bench: one GPU's share of a t-split over 8 GPUs %s" % (shard,))
 
     rhmc = None
     if not args.no_rhmc:
@@ -718,6 +760,7 @@ def main():
         action=action,
         force=force,
         operators=operators,
+        shard_local=shard,
         rhmc=rhmc,
         per_vector=dict(value=round(pv_rate, 4) if pv_rate == pv_rate else None,
                         unit="RHS-solves/s", columns=args.baseline_cols,
