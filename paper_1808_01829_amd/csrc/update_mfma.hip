@@ -35,6 +35,22 @@ typedef float fx4 __attribute__((ext_vector_type(4)));
 
 constexpr int MF_WAVES = BMS_WG / 64;
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glob_void;
+
+// Copy `bytes` rounded up to whole KiB (both regions hold that much) from
+// global memory into LDS by direct-to-LDS loads (global_load_lds_dwordx4, lane
+// l of a wave writing 16 bytes at the wave's destination + 16 l): wave w
+// copies the KiB chunks w, w + 4, ... Nothing passes through registers, so
+// every load of a shift's coefficients is in flight at once instead of one
+// round trip per matrix.
+__device__ __forceinline__ void lds_copy(const void* src, void* dst, int bytes, int wave,
+                                         int lane) {
+  for (int off = wave * 1024; off < bytes; off += MF_WAVES * 1024)
+    __builtin_amdgcn_global_load_lds((glob_void*)((const char*)src + off + lane * 16),
+                                     (lds_void*)((char*)dst + off), 16, 0, 0);
+}
+
 template <typename F>
 struct Mf;
 template <>
@@ -393,15 +409,12 @@ void k_update_mfma(UpdateArgs<F, F> a) {
     mask &= mask - 1;
     const int s2 = mask ? __ffsll((long long)mask) - 1 : -1;
     const int j = __builtin_amdgcn_readfirstlane(fl->win_j[slot][s]);
-    // the window's 2j coefficient matrices into LDS
+    // the window's 2j coefficient matrices into LDS (complex n x n, the X
+    // family, then the P family MW matrices further)
     const CF* wm = a.Wm + (size_t)s * 2 * FAM;
-    for (int e = tid; e < j * N * N; e += BMS_WG) {
-      const CF vx = wm[e], vp = wm[FAM + e];
-      sb[2 * e] = vx.x;
-      sb[2 * e + 1] = vx.y;
-      sb[2 * MW * N * N + 2 * e] = vp.x;
-      sb[2 * MW * N * N + 2 * e + 1] = vp.y;
-    }
+    lds_copy(wm, sb, j * N * N * (int)sizeof(CF), wave, lane);
+    lds_copy(wm + FAM, sb + 2 * MW * N * N, j * N * N * (int)sizeof(CF), wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const F* bx = sb;
     const F* bp = sb + 2 * MW * N * N;
