@@ -175,3 +175,32 @@ def test_hop_link_rows(torch, dims, n):
     c.set_gauge(to_dev(torch, U))
     assert c.link_rows() == 2
     c.close()
+
+
+def test_link_form_follows_the_field(torch):
+    """One context alternating between SU(3) links (read as two rows) and the
+    improved operator's one-hop and three-hop links (nine entries, not SU(3)):
+    each hop equals the oracle's for the field loaded last."""
+    from paper_1808_01829_amd import bms
+    dims, n, bc = (4, 4, 6, 4), 4, (1, 1, 1, -1)
+    U = random_gauge(dims, 0.6, 107)
+    V, W = U * (9.0 / 8.0), random_gauge(dims, 0.6, 108) * (-1.0 / 24.0)
+    v = gaussian_block(dims, n, 109)
+    vd = to_dev(torch, v)
+    c = _ctx(dims, bc, U)
+    for step in range(3):
+        improved = step == 1
+        if improved:
+            c.set_gauge_improved(to_dev(torch, V), to_dev(torch, W))
+        elif step == 2:
+            c.set_gauge(to_dev(torch, U))
+        rows, dev = c.link_rows(with_deviation=True)
+        assert rows == (3 if improved else 2)
+        assert (dev == -1.0) if improved else (0 <= dev <= 1e-14)
+        for par in (0, 1):
+            if improved:
+                ref = np.stack([O.dslash_half(dims, bc, V, par, v[..., j], W) for j in range(n)], -1)
+            else:
+                ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], -1)
+            assert rel(to_np(c.apply_hop(par, vd)), ref) < 1e-13
+    c.close()
