@@ -309,6 +309,91 @@ def operator_block_gain(bms, torch, dims, Ud, reps=5):
     return out
 
 
+# traversals of the half hop timed by --hop-traversal: (ty, tz, tt, cap, nt),
+# ty = 0 the natural site order (tiles otherwise), cap the resident
+# work-groups per compute unit (0: none), nt the non-temporal link hint
+HOP_TRAVERSALS = {
+    "f64": [(0, 0, 0, c, 1) for c in range(5)] + [(8, 8, 8, c, 1) for c in range(1, 5)] +
+           [(8, 8, 8, 2, 0), (8, 8, 4, 2, 1), (4, 4, 8, 2, 1), (16, 16, 2, 2, 1), (32, 8, 1, 2, 1)],
+    "f32": [(0, 0, 0, c, 1) for c in range(5)] +
+           [(8, 8, 8, 1, 1), (8, 8, 8, 2, 1), (4, 4, 8, 2, 1), (16, 16, 2, 2, 1), (32, 8, 1, 2, 1)],
+}
+
+
+def hop_traversal(bms, torch, dims, eps, n, reps=5):
+    """Each half hop (both parities, n columns, two-row links when the field
+    passes the check) under every traversal of HOP_TRAVERSALS: one untimed
+    launch, then `reps` launches timed with HIP events. The launch order is
+    fixed (precision, traversal, parity; 1 + reps launches each), so a
+    counter run of the same command maps its hop dispatches onto these rows."""
+    from paper_1808_01829_amd.inputs import gaussian_block, random_gauge
+    ctx = bms.Context(dims, (1, 1, 1, -1))
+    ctx.set_gauge(torch.from_numpy(random_gauge(dims, eps, 7201)).cuda())
+    v = torch.from_numpy(gaussian_block(dims, n, 7202)).cuda()
+    rows = []
+    for prec, name in ((bms.BMS_PREC_F64, "f64"), (bms.BMS_PREC_F32, "f32")):
+        x = v if name == "f64" else v.to(torch.complex64)
+        for cfg in HOP_TRAVERSALS[name]:
+            ctx.set_hop_config(prec, cfg)
+            for par in (1, 0):
+                ctx.apply_hop(par, x, prec)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    ctx.apply_hop(par, x, prec)
+                e1.record()
+                torch.cuda.synchronize()
+                rows.append(dict(prec=name, cfg=list(cfg), par=par,
+                                 us=round(e0.elapsed_time(e1) * 1e3 / reps, 1)))
+        ctx.set_hop_config(prec, None)
+    out = dict(lattice=list(dims), n=n, link_rows=ctx.link_rows(), reps=reps, rows=rows)
+    ctx.close()
+    return out
+
+
+def write_hop_traversal(fetch_csv, pmc_json, time_json, cal_fetch_csv, command, out_path):
+    """A text table of --hop-traversal: per traversal and parity the time (a
+    run without the profiler), and the FETCH_SIZE of one rocprofv3 --pmc run of
+    the same command (median over the timed launches, scaled by the 1 GiB copy
+    calibration), as bytes and as multiples of the block vector read."""
+    fetch_factor, _ = copy_factor(cal_fetch_csv)
+    hop = [v for k, v in _counter_rows(fetch_csv) if "k_hop" in k]
+    run = json.loads([l for l in open(pmc_json) if l.startswith("{")][-1])
+    tim = json.loads([l for l in open(time_json) if l.startswith("{")][-1])
+    per = 1 + run["reps"]
+    if len(hop) != per * len(run["rows"]):
+        raise SystemExit("hop dispatches %d, expected %d" % (len(hop), per * len(run["rows"])))
+    dims, n = run["lattice"], run["n"]
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    epl = 6 if run["link_rows"] == 2 else 9
+    lines = ["# Half hop by traversal, %s lattice, n = %d, %d-entry links" %
+             ("x".join(map(str, dims)), n, epl), "",
+             "commands:",
+             "  python3 bench.py --hop-traversal        (times: HIP events, %d launches each)" %
+             run["reps"],
+             "  " + command,
+             "  python3 bench.py --write-hop-traversal <fetch csv> <pmc run json> "
+             "<time run json> <copy fetch csv>",
+             "fetch: FETCH_SIZE per dispatch x %.4f (1 GiB copy calibration); "
+             "S = one block vector, G = the links" % fetch_factor, "",
+             "prec  traversal (ty,tz,tt,cap,nt)  par     us   fetch MB   (fetch - G) / S   "
+             "fetch GB/s"]
+    for i, (r, t) in enumerate(zip(run["rows"], tim["rows"])):
+        b = 8 if r["prec"] == "f64" else 4
+        S = vh * 3 * n * 2 * b
+        G = vh * 8 * epl * 2 * b
+        vals = sorted(hop[i * per + 1:(i + 1) * per])
+        f = vals[len(vals) // 2] * 1024 * fetch_factor
+        lines.append("%-5s %-28s %3d %7.1f %10.1f %17.2f %12.0f" %
+                     (r["prec"], tuple(r["cfg"]), r["par"], t["us"], f / 1e6, (f - G) / S,
+                      f / (t["us"] * 1e-6) / 1e9))
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    return out_path
+
+
 def rhmc_measure(bms, torch, np, configs):
     """One RHMC trajectory at the paper's settings (force solves at 1e-7,
     heatbath and action at 1e-14, two-level Omelyan with lambda = 1/6, three
@@ -490,12 +575,27 @@ def main():
                     help="with --write-traffic: folder of the JSON file")
     ap.add_argument("--profile-command", default="",
                     help="with --write-traffic: the command the counter runs used ({} = counter)")
+    ap.add_argument("--hop-traversal", action="store_true",
+                    help="only the half hops of the workload under a fixed list of traversals "
+                         "(times per launch, one JSON line)")
+    ap.add_argument("--write-hop-traversal", nargs=4,
+                    metavar=("FETCH_CSV", "PMC_RUN_JSON", "TIME_RUN_JSON", "CAL_FETCH_CSV"),
+                    help="write profiles/hop_traversal_<workload>.txt from a FETCH_SIZE run and "
+                         "a plain run of --hop-traversal; then exit (no GPU)")
     ap.add_argument("--trace-gaps", metavar="KERNEL_TRACE_CSV", default=None,
                     help="print the GPU idle time inside the first solve of a rocprofv3 "
                          "kernel trace of this benchmark; then exit (no GPU)")
     args = ap.parse_args()
     if args.trace_gaps:
         print(json.dumps(trace_gaps(args.trace_gaps)))
+        return
+    if args.write_hop_traversal:
+        fcsv, prun, trun, cfcsv = args.write_hop_traversal
+        cmd = ("rocprofv3 --pmc FETCH_SIZE --kernel-include-regex k_hop --output-format csv "
+               "-d <dir> -o run -- python3 -u bench.py --hop-traversal")
+        print(write_hop_traversal(fcsv, prun, trun, cfcsv, cmd,
+                                  os.path.join(args.traffic_out,
+                                               "hop_traversal_%s.txt" % args.workload)))
         return
     if args.write_traffic:
         prec, fcsv, wcsv, cfcsv, cwcsv, run = args.write_traffic
@@ -532,6 +632,10 @@ def main():
         return
     if args.force_only:
         print(json.dumps(force_measure(bms, torch, np, configs)), flush=True)
+        return
+    if args.hop_traversal:
+        w = configs.WORKLOADS[args.workload]
+        print(json.dumps(hop_traversal(bms, torch, w["dims"], w["eps"], w["n"])), flush=True)
         return
 
     w = configs.WORKLOADS[args.workload]
