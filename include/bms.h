@@ -419,8 +419,12 @@ int bms_timing_enable(bms_ctx* ctx, int enable);
  * (n = 4, 8, 16, 32), 0 = one thread per site and column group, 2 and 3 = 0
  * and 1 in a tiled traversal (8 x 8 x 4 tiles in y, z, t of whole x-rows,
  * each (y, z) pencil on one XCD; lattices the tiles do not fit run in the
- * natural order), -1 = the default (1 where it applies, tiled in FP64 at
- * n >= 16). For BMS_KERNEL_FORCE: 1 and 2 = the fused kernel (y = D_oe x
+ * natural order), 4 = at n = 16 persistent waves that keep the next hops'
+ * columns and links in flight through a ring in LDS (direct-to-LDS loads;
+ * for lattices with V/2 a multiple of 128 and a ring that fits one
+ * work-group's LDS, else variant 1; the hop configuration's tiles apply and
+ * its cap is the ring depth, 2 or 4), -1 = the default (1 where it applies,
+ * tiled in FP64 at n >= 16). For BMS_KERNEL_FORCE: 1 and 2 = the fused kernel (y = D_oe x
  * formed on chip for all n * n_shifts columns, each link loaded once and
  * written once; links in registers, or in LDS with the loads two columns
  * ahead), 0 = D_oe hops per shift into a buffer, then one lane group per

@@ -333,7 +333,7 @@ extern "C" int bms_timing_floor(const bms_ctx* c, int kernel, double hbm_bytes_p
 extern "C" int bms_set_variant(bms_ctx* c, int kernel, int variant) {
   if (!c) return BMS_EINVAL;
   if (kernel == BMS_KERNEL_HOP) {
-    if (variant < -1 || variant > 3) return set_err(c, BMS_EINVAL, "hop variant must be in [-1, 3]");
+    if (variant < -1 || variant > 4) return set_err(c, BMS_EINVAL, "hop variant must be in [-1, 4]");
     c->hop_variant = variant;
     return BMS_OK;
   }

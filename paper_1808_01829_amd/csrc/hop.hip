@@ -191,9 +191,9 @@ struct HopTiles {
   int spb;           // sites per work-group
 };
 
-// first checkerboard site of this work-group's sites
-__device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom& g) {
-  const uint32_t b = blockIdx.x;
+// first checkerboard site of block b of the tiled order (block b belongs to
+// XCD b % 8; blocks of m.spb sites)
+__device__ __forceinline__ uint32_t hop_block_site(const HopTiles& m, const Geom& g, uint32_t b) {
   const uint32_t x = b & 7, j = b >> 3;
   const uint32_t per_pencil = (uint32_t)(m.bpt * m.tpp);
   const uint32_t pencil = x + 8u * (j / per_pencil);
@@ -207,6 +207,11 @@ __device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom
   const uint32_t zl = r2 % (uint32_t)m.tz, tl = r2 / (uint32_t)m.tz;
   const uint32_t y = py * m.ty + yl, z = pz * m.tz + zl, t = tile_t * m.tt + tl;
   return (uint32_t)g.hx * (y + (uint32_t)g.L[1] * (z + (uint32_t)g.L[2] * t));
+}
+
+// first checkerboard site of this work-group's sites
+__device__ __forceinline__ uint32_t hop_first_site(const HopTiles& m, const Geom& g) {
+  return hop_block_site(m, g, blockIdx.x);
 }
 
 // out(s) = b * sum_k L_k(s) in(nbr_k(s)) + a * aux(s) on n columns.
@@ -386,6 +391,295 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
     }
 }
 
+
+typedef __attribute__((address_space(3))) void hop_lds_void;
+typedef __attribute__((address_space(1))) void hop_glob_void;
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// s_waitcnt immediate that waits until at most n vector memory operations
+// are outstanding (n < 64) and leaves the other counters alone
+constexpr int vm_wait(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+// Direct-to-LDS loads of a wave: lane l's 16 (4) bytes go to dst + 16 l
+// (dst + 4 l); CP is the cache policy (2: non-temporal).
+template <int CP = 0>
+__device__ __forceinline__ void dma16(const void* src, unsigned char* dst) {
+  __builtin_amdgcn_global_load_lds((const hop_glob_void*)src, (hop_lds_void*)dst, 16, 0, CP);
+}
+template <int CP = 0>
+__device__ __forceinline__ void dma4(const void* src, unsigned char* dst) {
+  __builtin_amdgcn_global_load_lds((const hop_glob_void*)src, (hop_lds_void*)dst, 4, 0, CP);
+}
+__device__ __forceinline__ uint32_t lds_addr(const unsigned char* p) {
+  return (uint32_t)(uintptr_t)(const hop_lds_void*)p;
+}
+
+// Bytes of one ring slot of k_hop_s: the neighbour columns of 16 sites for
+// one hop (48 complex per site), then the link entries the wave's lanes load.
+template <typename T, int EPL>
+constexpr int hop_s_slot() {
+  return 16 * 48 * (int)sizeof(cplx<T>) + (EPL == 9 ? 3 : 2) * (sizeof(T) == 8 ? 1024 : 512);
+}
+// LDS of one k_hop_s wave: D slots and the group's aux columns
+template <typename T, int EPL>
+constexpr int hop_s_wave_lds(int d) {
+  return d * hop_s_slot<T, EPL>() + 16 * 48 * (int)sizeof(cplx<T>);
+}
+
+// The half hop at n = 16 with the next hops' loads in flight. A thread quad
+// per site as in k_hop_q (FP64: columns q + 4r; FP32: columns 4q .. 4q+3).
+// Every wave runs its own list of 16-site groups, hop after hop, through a
+// ring of D slots in LDS: while it computes one hop from its slot, the
+// neighbour columns and link entries of the next D-1 hops are on their way by
+// direct-to-LDS loads (a wave's 64 lanes fill one contiguous run, so a lane
+// reads back exactly what it loaded). Loads complete in issue order, so
+// waiting until at most (D-1) hops of loads are outstanding completes the
+// slot (any other load issued in between only lengthens the wait). Nothing
+// is loaded into registers: the compiler cannot order its own waits for a
+// register load against direct-to-LDS loads and would wait for all of them.
+// So the epilogue's aux columns come with the group's last hop into an area
+// of their own, and with two-row links the lanes q = 2, 3 of a site, whose
+// second link entry only repeats that of q = 0, 1, fetch the site's sign
+// mask instead. A wave touches only its own LDS: no barriers. The grid is
+// persistent (a multiple of 8 work-groups): group j of XCD x (the
+// work-groups b with b % 8 = x) is block 8j + x of the traversal (tiled:
+// hop_block_site with 16-site blocks; natural: sites 16 (8j + x) ..), and
+// the XCD's waves take its groups in turn, so they sweep the same part of
+// the lattice together.
+template <typename T, bool NT, int NL, int EPL, int D>
+__global__ __launch_bounds__(BMS_WG) void k_hop_s(const cplx<T>* __restrict__ links,
+                                                  const cplx<T>* __restrict__ in,
+                                                  cplx<T>* __restrict__ out,
+                                                  const cplx<T>* __restrict__ aux, T a, T b,
+                                                  Geom g, int par, int sbl,
+                                                  const int* __restrict__ skip, HopTiles tiles,
+                                                  const uint32_t* __restrict__ sgn, int gpx) {
+  using C = cplx<T>;
+  constexpr int N = 16, R = 4;
+  constexpr bool kF64 = sizeof(T) == 8;
+  constexpr int IN = 16 * 48 * (int)sizeof(C);  // neighbour columns of one hop
+  constexpr int SLOT = hop_s_slot<T, EPL>();
+  constexpr int NLK = EPL == 9 ? 3 : 2;                    // link entries per lane
+  constexpr int OPS = IN / 1024 + (kF64 ? NLK : 2 * NLK);  // loads per hop and wave
+  constexpr int CP = NT ? 2 : 0;
+  static_assert(NL % D == 0 && (D - 1) * OPS < 64, "ring depth");
+  extern __shared__ __align__(16) unsigned char hs_lds[];
+  if (skip && *skip) return;
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  const int q = lane & 3, ls = lane >> 2;
+  unsigned char* ring = hs_lds + wave * hop_s_wave_lds<T, EPL>(D);
+  unsigned char* auxa = ring + D * SLOT;
+  const uint32_t xcd = blockIdx.x & 7;
+  const uint32_t u = (blockIdx.x >> 3) * (BMS_WG / 64) + (uint32_t)wave;
+  const uint32_t U = (gridDim.x >> 3) * (BMS_WG / 64);
+  const int ng = u < (uint32_t)gpx ? (int)(((uint32_t)gpx - 1 - u) / U) + 1 : 0;
+  const int nt = ng * NL;  // hops this wave runs
+  const size_t st = (size_t)1 << sbl;
+  const int e1 = EPL == 6 ? 4 + (q & 1) : q + 4;
+  const int e2 = q == 0 ? 8 : q + 4;
+  auto group_site = [&](int i) {
+    const uint32_t bk = 8u * (u + (uint32_t)i * U) + xcd;
+    return (tiles.on ? hop_block_site(tiles, g, bk) : 16u * bk) + (uint32_t)ls;
+  };
+  // the prefetch side: the site of the group whose hops are being requested
+  uint32_t ps = 0;
+  SiteCoord pc{};
+  // 16 bytes of column data per lane and load: FP64 column q + 4r, FP32
+  // bytes 16r .. 16r+15 of columns 4q .. 4q+3 (r < 4 in FP64, < 2 in FP32)
+  auto col_ptr = [&](const C* row, int cb, int r) {
+    return kF64 ? (const void*)(row + cb * N + q + 4 * r)
+                : (const void*)((const char*)(row + cb * N + 4 * q) + 16 * r);
+  };
+  auto prefetch = [&](int i, int k, int slot) {
+    if (k == 0) {
+      ps = group_site(i);
+      pc = site_coords(ps, g, par);
+    }
+    const int nb = neighbour_cb((int)ps, pc, g, k & 3, hop_dist(k));
+    const C* src = in + (size_t)nb * 3 * N;
+    unsigned char* dst = ring + slot * SLOT;
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+      for (int r = 0; r < IN / 3 / 1024; ++r)
+        dma16(col_ptr(src, cb, r), dst + (cb * (IN / 3 / 1024) + r) * 1024);
+    const C* L = links + link_off(ps, k, 0, sbl, EPL * NL, EPL);
+    // two-row links: lanes q = 2, 3 fetch the sign masks (FP64: the aligned
+    // 16 bytes holding the site's)
+    const bool mlane = EPL == 6 && q >= 2;
+    const void* le[3] = {L + q * st,
+                         mlane ? (const void*)(sgn + (kF64 ? (ps & ~3u) : ps))
+                               : (const void*)(L + e1 * st),
+                         L + e2 * st};
+#pragma unroll
+    for (int e = 0; e < NLK; ++e) {
+      if constexpr (kF64) {
+        dma16<CP>(le[e], dst + IN + e * 1024);
+      } else {
+        dma4<CP>(le[e], dst + IN + e * 512);
+        dma4<CP>(e == 1 && mlane ? le[e] : (const void*)((const float*)le[e] + 1),
+                 dst + IN + e * 512 + 256);
+      }
+    }
+    if (aux && k == NL - 1) {
+      const C* ar = aux + (size_t)ps * 3 * N;
+#pragma unroll
+      for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+        for (int r = 0; r < IN / 3 / 1024; ++r)
+          dma16(col_ptr(ar, cb, r), auxa + (cb * (IN / 3 / 1024) + r) * 1024);
+    }
+  };
+  // LDS reads the compiler does not see: one it sees after a direct-to-LDS
+  // load makes it wait for every load in flight (it cannot tell the slots
+  // apart), which would drain the ring at every hop. Each block completes
+  // its reads before it ends, and its outputs are early-clobber (a read must
+  // not land in the address register the later reads of the block use).
+  // 12 (FP64) or 6 (FP32) 16-byte columns per lane from `cols`:
+  auto read_cols = [&](const unsigned char* cols, C (&v)[3][R]) {
+    const uint32_t la = lds_addr(cols + 16 * lane);
+    if constexpr (kF64) {
+      d2v w[12];
+      asm volatile(
+          "ds_read_b128 %0, %12\n ds_read_b128 %1, %12 offset:1024\n"
+          "ds_read_b128 %2, %12 offset:2048\n ds_read_b128 %3, %12 offset:3072\n"
+          "ds_read_b128 %4, %12 offset:4096\n ds_read_b128 %5, %12 offset:5120\n"
+          "ds_read_b128 %6, %12 offset:6144\n ds_read_b128 %7, %12 offset:7168\n"
+          "ds_read_b128 %8, %12 offset:8192\n ds_read_b128 %9, %12 offset:9216\n"
+          "ds_read_b128 %10, %12 offset:10240\n ds_read_b128 %11, %12 offset:11264\n"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5]),
+            "=&v"(w[6]), "=&v"(w[7]), "=&v"(w[8]), "=&v"(w[9]), "=&v"(w[10]), "=&v"(w[11])
+          : "v"(la));
+#pragma unroll
+      for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[cb][r] = make_double2(w[cb * R + r].x, w[cb * R + r].y);
+    } else {
+      f4v w[6];
+      asm volatile(
+          "ds_read_b128 %0, %6\n ds_read_b128 %1, %6 offset:1024\n"
+          "ds_read_b128 %2, %6 offset:2048\n ds_read_b128 %3, %6 offset:3072\n"
+          "ds_read_b128 %4, %6 offset:4096\n ds_read_b128 %5, %6 offset:5120\n"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5])
+          : "v"(la));
+#pragma unroll
+      for (int cb = 0; cb < 3; ++cb) {
+        v[cb][0] = make_float2(w[2 * cb].x, w[2 * cb].y);
+        v[cb][1] = make_float2(w[2 * cb].z, w[2 * cb].w);
+        v[cb][2] = make_float2(w[2 * cb + 1].x, w[2 * cb + 1].y);
+        v[cb][3] = make_float2(w[2 * cb + 1].z, w[2 * cb + 1].w);
+      }
+    }
+  };
+  uint32_t cs = 0, cmsk = 0;
+  C acc[3][R];
+  auto compute = [&](int i, int k, int slot) {
+    const int t = i * NL + k;
+    if (t + D - 1 < nt)
+      __builtin_amdgcn_s_waitcnt(vm_wait((D - 1) * OPS));
+    else
+      __builtin_amdgcn_s_waitcnt(vm_wait(0));
+    const unsigned char* sp = ring + slot * SLOT;
+    C v[3][R], lt[3];
+    read_cols(sp, v);
+    if constexpr (kF64) {
+      d2v w[3];
+      asm volatile(
+          "ds_read_b128 %0, %3\n ds_read_b128 %1, %3 offset:1024\n"
+          "ds_read_b128 %2, %3 offset:2048\n s_waitcnt lgkmcnt(0)"
+          : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2])
+          : "v"(lds_addr(sp + IN + 16 * lane)));
+      // (the third word, past a two-row slot, lies in this wave's LDS and is unused)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) lt[e] = make_double2(w[e].x, w[e].y);
+    } else {
+      float w[6];
+      asm volatile(
+          "ds_read_b32 %0, %6\n ds_read_b32 %1, %6 offset:256\n"
+          "ds_read_b32 %2, %6 offset:512\n ds_read_b32 %3, %6 offset:768\n"
+          "ds_read_b32 %4, %6 offset:1024\n ds_read_b32 %5, %6 offset:1280\n"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5])
+          : "v"(lds_addr(sp + IN + 4 * lane)));
+#pragma unroll
+      for (int e = 0; e < 3; ++e) lt[e] = make_float2(w[2 * e], w[2 * e + 1]);
+    }
+    if (k == 0) {
+      cs = group_site(i);
+      if constexpr (EPL == 6) {
+        // lane q = 2 of the site holds its mask (FP64: word cs % 4 of the 16 bytes)
+        uint32_t m;
+        if constexpr (kF64) {
+          const uint64_t lo = __builtin_bit_cast(uint64_t, lt[1].x);
+          const uint64_t hi = __builtin_bit_cast(uint64_t, lt[1].y);
+          const uint64_t h = (cs & 2) ? hi : lo;
+          m = (uint32_t)((cs & 1) ? (h >> 32) : h);
+        } else {
+          m = __builtin_bit_cast(uint32_t, lt[1].x);
+        }
+        cmsk = (uint32_t)__builtin_amdgcn_mov_dpp((int)m, 2 * 0x55, 0xF, 0xF, false);
+      }
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
+    }
+    C l[9];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const C own = e < 4 ? lt[0] : (e < 8 ? lt[1] : lt[2]);
+      switch (e & 3) {
+        case 0: l[e].x = quad_bcast<0>(own.x); l[e].y = quad_bcast<0>(own.y); break;
+        case 1: l[e].x = quad_bcast<1>(own.x); l[e].y = quad_bcast<1>(own.y); break;
+        case 2: l[e].x = quad_bcast<2>(own.x); l[e].y = quad_bcast<2>(own.y); break;
+        default: l[e].x = quad_bcast<3>(own.x); l[e].y = quad_bcast<3>(own.y);
+      }
+    }
+    if constexpr (EPL == 6) link_row2(l, (cmsk >> k) & 1);
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[cb][r], acc[a3][r]);
+    if (k == NL - 1) {
+      C ax[3][R];
+      if (aux) read_cols(auxa, ax);
+      const size_t o = (size_t)cs * 3 * N + (kF64 ? q : 4 * q);
+#pragma unroll
+      for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const size_t oo = o + a3 * N + r * (kF64 ? 4 : 1);
+          out[oo] = aux ? cadd(cscale(ax[a3][r], a), cscale(acc[a3][r], b)) : cscale(acc[a3][r], b);
+        }
+    }
+  };
+  if (ng == 0) return;
+#pragma unroll
+  for (int d = 0; d < D; ++d) prefetch(0, d, d);
+  for (int i = 0; i < ng; ++i) {
+    // D hops per iteration, unrolled: the ring slot of each is a constant
+#pragma unroll 1
+    for (int k0 = 0; k0 < NL; k0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int k = k0 + d;
+        compute(i, k, d);
+        // the slot's values are in registers (the reads completed) before it refills
+        __builtin_amdgcn_sched_barrier(0);
+        if (k + D < NL)
+          prefetch(i, k + D, d);
+        else if (i + 1 < ng)
+          prefetch(i + 1, k + D - NL, d);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gauge_import(const bms_ctx* c, const void* U, void* l64, void* l32,
@@ -466,6 +760,29 @@ HopPlan hop_plan(const bms_ctx* c, int n, bool fp64) {
   // inside each XCD's L2 (at 32^4 FP64 n = 16 513 -> 455 us natural order).
   p.cap = hc.cap >= 0 ? hc.cap : (n >= 16 ? 2 : (n == 8 ? 3 : 0));
   p.nt = hc.nt > 0;
+  // Variant 4 (n = 16, whole groups of 16 sites over 8 XCDs): the streamed
+  // kernel, tiled unless the configuration asks for the natural order; the
+  // configuration's cap is its ring depth (2 or 4 slots per wave; the
+  // default 2 in FP64, 4 in FP32).
+  if (hv == 4 && n == 16 && c->vh % 128 == 0) {
+    // LDS of a work-group (four waves) at ring depth d; a depth that does not
+    // fit falls back to 2, and if that does not fit either the quad kernel runs
+    const bool two = c->links_two_rows && c->nlinks == 8;
+    const auto bytes = [&](int d) {
+      return (BMS_WG / 64) *
+             (fp64 ? (two ? hop_s_wave_lds<double, 6>(d) : hop_s_wave_lds<double, 9>(d))
+                   : (two ? hop_s_wave_lds<float, 6>(d) : hop_s_wave_lds<float, 9>(d)));
+    };
+    int d = hc.cap >= 4 ? 4 : (hc.cap >= 2 ? 2 : (fp64 ? 2 : 4));
+    if (d == 4 && bytes(4) > c->lds_per_block) d = 2;
+    if (bytes(d) <= c->lds_per_block) {
+      p.stream = true;
+      p.quad = false;
+      p.tiled = hc.ty != 0;
+      p.depth = d;
+      p.cap = 0;
+    }
+  }
   return p;
 }
 
@@ -485,6 +802,46 @@ hipError_t launch_hop(const bms_ctx* c, int par, int n, const void* in, void* ou
   // tile extents, resident cap and link-load hint come from the context's
   // hop configuration (bms_set_hop_config, bms_autotune).
   const HopPlan hp = hop_plan(c, n, sizeof(T) == 8);
+  if (hp.stream) {
+    // a ring of `depth` slots per wave and the group's aux columns; a
+    // persistent grid of whole groups of 8 work-groups, as many per compute
+    // unit as the LDS holds
+    const int d = hp.depth;
+    const size_t lds = (size_t)(BMS_WG / 64) *
+                       (two ? hop_s_wave_lds<T, 6>(d) : hop_s_wave_lds<T, 9>(d));
+    int wpc = c->lds_per_cu > 0 ? c->lds_per_cu / (int)lds : 1;
+    wpc = wpc < 1 ? 1 : (wpc > 8 ? 8 : wpc);
+    int nblk = (c->num_cu > 0 ? c->num_cu : 8) * wpc;
+    nblk = nblk < 8 ? 8 : nblk - nblk % 8;
+    const HopTiles tiles = hp.tiled ? hop_tiles(c, 16, hp.ty, hp.tz, hp.tt) : HopTiles{};
+    const int gpx = c->vh / 128;
+#define HOPS(NT, NL, EPL, DD)                                                              \
+  k_hop_s<T, NT, NL, EPL, DD><<<nblk, BMS_WG, lds, c->stream>>>(                           \
+      links, (const cplx<T>*)in, (cplx<T>*)out, (const cplx<T>*)aux, (T)a, (T)b, c->geom,  \
+      par, c->sbl, skip, tiles, sgn, gpx)
+#define HOPSD(NT, NL, EPL) \
+  if (d == 2)              \
+    HOPS(NT, NL, EPL, 2);  \
+  else                     \
+    HOPS(NT, NL, EPL, 4)
+#define HOPSN(NT)             \
+  if (c->nlinks == 16) {      \
+    HOPSD(NT, 16, 9);         \
+  } else if (two) {           \
+    HOPSD(NT, 8, 6);          \
+  } else {                    \
+    HOPSD(NT, 8, 9);          \
+  }
+    if (hp.nt) {
+      HOPSN(true)
+    } else {
+      HOPSN(false)
+    }
+#undef HOPSN
+#undef HOPSD
+#undef HOPS
+    return hipGetLastError();
+  }
   const size_t lds = hop_cap_lds(c, hp.cap);
   if (hp.quad) {
     dim3 qgrid((4u * (uint32_t)c->vh + BMS_WG - 1) / BMS_WG);

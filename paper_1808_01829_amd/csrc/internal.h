@@ -85,6 +85,8 @@ struct HopCfg {
 struct HopPlan {
   bool quad = false, tiled = false, nt = false;
   int ty = 8, tz = 8, tt = 4, cap = 0;
+  bool stream = false;  // k_hop_s: persistent waves with `depth` hops in flight
+  int depth = 0;
 };
 
 struct bms_ctx {

@@ -204,3 +204,61 @@ def test_link_form_follows_the_field(torch):
                 ref = np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], -1)
             assert rel(to_np(c.apply_hop(par, vd)), ref) < 1e-13
     c.close()
+
+
+def test_hop_streamed(torch):
+    """The streamed half hop (variant 4, n = 16: persistent waves, the next
+    hops' columns and links in flight through a ring in LDS) against the
+    oracle: tiled and natural traversals, ring depths 2 and 4, with and
+    without the non-temporal link hint, FP64 and FP32, two-row and nine-entry
+    SU(3) links and the improved operator, the D_eo hop with its aux term,
+    and lattices it does not take (another kernel runs)."""
+    from paper_1808_01829_amd import bms
+    dims, bc, n = (16, 16, 32, 4), (1, 1, 1, -1), 16
+    U = random_gauge(dims, 0.7, 111)
+    v = gaussian_block(dims, n, 112)
+    vd, v32 = to_dev(torch, v), to_dev(torch, v.astype(np.complex64))
+    ref = {par: np.stack([O.dslash_half(dims, bc, U, par, v[..., j]) for j in range(n)], axis=-1)
+           for par in (0, 1)}
+    mref = O.mdagm(dims, bc, U, 0.05, 0.3, v)
+    c = _ctx(dims, bc, U)
+    c.set_variant(bms.BMS_KERNEL_HOP, 4)
+    cfgs = [None, (8, 8, 4, 2, 1), (8, 8, 4, 4, 0), (0, 0, 0, 2, 0), (0, 0, 0, 4, 1), (16, 8, 4, 4, 1)]
+    for rows in (2, 3):
+        c.set_link_rows(rows)
+        c.set_gauge(to_dev(torch, U))
+        assert c.link_rows() == rows
+        for cfg in cfgs:
+            for prec in (bms.BMS_PREC_F64, bms.BMS_PREC_F32):
+                c.set_hop_config(prec, cfg)
+            for par in (0, 1):
+                out = to_np(c.apply_hop(par, vd))
+                assert rel(out, ref[par]) < 1e-13, (rows, cfg, par)
+                out32 = to_np(c.apply_hop(par, v32, bms.BMS_PREC_F32))
+                assert rel(out32, ref[par]) < 2e-6, (rows, cfg, par)
+            assert rel(to_np(c.apply_mdagm(0.05, 0.3, vd)), mref) < 1e-13, (rows, cfg)
+            m32 = to_np(c.apply_mdagm(0.05, 0.3, v32, bms.BMS_PREC_F32))
+            assert rel(m32, mref) < 2e-6, (rows, cfg)
+    # the improved operator (16 links per site)
+    V = random_gauge(dims, 0.7, 113) * (9.0 / 8.0)
+    W = random_gauge(dims, 0.7, 114) * (-1.0 / 24.0)
+    c.set_gauge_improved(to_dev(torch, V), to_dev(torch, W))
+    for cfg in (None, (0, 0, 0, 2, 1)):
+        for prec in (bms.BMS_PREC_F64, bms.BMS_PREC_F32):
+            c.set_hop_config(prec, cfg)
+        for par in (0, 1):
+            r = np.stack([O.dslash_half(dims, bc, V, par, v[..., j], W) for j in range(n)], axis=-1)
+            assert rel(to_np(c.apply_hop(par, vd)), r) < 1e-13, (cfg, par)
+            assert rel(to_np(c.apply_hop(par, v32, bms.BMS_PREC_F32)), r) < 2e-6, (cfg, par)
+    c.close()
+    # lattices the streamed kernel does not take (V/2 not a multiple of 128,
+    # n != 16) run another kernel with the same result
+    for dims2, n2 in (((4, 6, 2, 8), 16), ((8, 8, 8, 8), 8)):
+        U2 = random_gauge(dims2, 0.7, 115)
+        v2 = gaussian_block(dims2, n2, 116)
+        c2 = _ctx(dims2, bc, U2)
+        c2.set_variant(bms.BMS_KERNEL_HOP, 4)
+        for par in (0, 1):
+            r = np.stack([O.dslash_half(dims2, bc, U2, par, v2[..., j]) for j in range(n2)], axis=-1)
+            assert rel(to_np(c2.apply_hop(par, to_dev(torch, v2))), r) < 1e-13, (dims2, par)
+        c2.close()
