@@ -131,3 +131,25 @@ def test_uneven_batch_mixed_precision(torch):
         assert np.array_equal(to_np(X1), to_np(Xs[i]))
         tr = O.true_residuals(dims, BC, Us[i], 0.05, shifts[i], to_np(Bs[i]), to_np(Xs[i]))
         assert tr.max() <= 1e-10
+
+
+def test_streamed_hop_solves(torch):
+    """Solves whose half hops run the streamed kernel (variant 4) inside the
+    captured iteration chunks: true residuals within tol and the iteration
+    counts of the default kernel's solves (the results differ only by
+    rounding order)."""
+    from paper_1808_01829_amd import bms
+    r = configs.workload_coefficients("c2")
+    dims = (8, 8, 8, 8)
+    ctx, U, B = _problem(torch, dims, 16, 61)
+    Bd = to_dev(torch, B)
+    for prec in (bms.BMS_PREC_F64, bms.BMS_PREC_MIXED):
+        its = {}
+        for v in (-1, 4):
+            ctx.set_variant(bms.BMS_KERNEL_HOP, v)
+            X, st = ctx.solve(0.05, r.beta, Bd, tol=1e-10, precision=prec)
+            tr = O.true_residuals(dims, BC, U, 0.05, r.beta, B, to_np(X))
+            assert tr.max() <= 1e-10, (prec, v)
+            its[v] = st["iterations"]
+        assert abs(its[4] - its[-1]) <= 2, (prec, its)
+    ctx.close()
