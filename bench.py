@@ -311,20 +311,24 @@ def operator_block_gain(bms, torch, dims, Ud, reps=5):
 
 # traversals of the half hop timed by --hop-traversal: (ty, tz, tt, cap, nt),
 # ty = 0 the natural site order (tiles otherwise), cap the resident
-# work-groups per compute unit (0: none), nt the non-temporal link hint
+# work-groups per compute unit (0: none), nt the non-temporal link hint; all
+# with the default kernel, then the streamed kernel (hop variant 4, whose cap
+# is its ring depth)
 HOP_TRAVERSALS = {
     "f64": [(0, 0, 0, c, 1) for c in range(5)] + [(8, 8, 8, c, 1) for c in range(1, 5)] +
            [(8, 8, 8, 2, 0), (8, 8, 4, 2, 1), (4, 4, 8, 2, 1), (16, 16, 2, 2, 1), (32, 8, 1, 2, 1)],
     "f32": [(0, 0, 0, c, 1) for c in range(5)] +
            [(8, 8, 8, 1, 1), (8, 8, 8, 2, 1), (4, 4, 8, 2, 1), (16, 16, 2, 2, 1), (32, 8, 1, 2, 1)],
 }
+HOP_STREAMED = [(8, 8, 8, 2, 1), (8, 8, 4, 2, 0), (8, 8, 8, 4, 1), (0, 0, 0, 2, 1), (0, 0, 0, 4, 1)]
 
 
 def hop_traversal(bms, torch, dims, eps, n, reps=5):
     """Each half hop (both parities, n columns, two-row links when the field
-    passes the check) under every traversal of HOP_TRAVERSALS: one untimed
-    launch, then `reps` launches timed with HIP events. The launch order is
-    fixed (precision, traversal, parity; 1 + reps launches each), so a
+    passes the check) under every traversal of HOP_TRAVERSALS with the default
+    kernel and of HOP_STREAMED with the streamed one: one untimed launch, then
+    `reps` launches timed with HIP events. The launch order is fixed
+    (precision, kernel and traversal, parity; 1 + reps launches each), so a
     counter run of the same command maps its hop dispatches onto these rows."""
     from paper_1808_01829_amd.inputs import gaussian_block, random_gauge
     ctx = bms.Context(dims, (1, 1, 1, -1))
@@ -333,7 +337,8 @@ def hop_traversal(bms, torch, dims, eps, n, reps=5):
     rows = []
     for prec, name in ((bms.BMS_PREC_F64, "f64"), (bms.BMS_PREC_F32, "f32")):
         x = v if name == "f64" else v.to(torch.complex64)
-        for cfg in HOP_TRAVERSALS[name]:
+        for variant, cfg in [(-1, c) for c in HOP_TRAVERSALS[name]] + [(4, c) for c in HOP_STREAMED]:
+            ctx.set_variant(bms.BMS_KERNEL_HOP, variant)
             ctx.set_hop_config(prec, cfg)
             for par in (1, 0):
                 ctx.apply_hop(par, x, prec)
@@ -345,8 +350,9 @@ def hop_traversal(bms, torch, dims, eps, n, reps=5):
                     ctx.apply_hop(par, x, prec)
                 e1.record()
                 torch.cuda.synchronize()
-                rows.append(dict(prec=name, cfg=list(cfg), par=par,
+                rows.append(dict(prec=name, variant=variant, cfg=list(cfg), par=par,
                                  us=round(e0.elapsed_time(e1) * 1e3 / reps, 1)))
+        ctx.set_variant(bms.BMS_KERNEL_HOP, -1)
         ctx.set_hop_config(prec, None)
     out = dict(lattice=list(dims), n=n, link_rows=ctx.link_rows(), reps=reps, rows=rows)
     ctx.close()
@@ -378,7 +384,8 @@ def write_hop_traversal(fetch_csv, pmc_json, time_json, cal_fetch_csv, command, 
              "<time run json> <copy fetch csv>",
              "fetch: FETCH_SIZE per dispatch x %.4f (1 GiB copy calibration); "
              "S = one block vector, G = the links" % fetch_factor, "",
-             "prec  traversal (ty,tz,tt,cap,nt)  par     us   fetch MB   (fetch - G) / S   "
+             "variant -1: the default kernel; 4: the streamed kernel (cap = its ring depth)", "",
+             "prec  var traversal (ty,tz,tt,cap,nt)  par     us   fetch MB   (fetch - G) / S   "
              "fetch GB/s"]
     for i, (r, t) in enumerate(zip(run["rows"], tim["rows"])):
         b = 8 if r["prec"] == "f64" else 4
@@ -386,9 +393,9 @@ def write_hop_traversal(fetch_csv, pmc_json, time_json, cal_fetch_csv, command, 
         G = vh * 8 * epl * 2 * b
         vals = sorted(hop[i * per + 1:(i + 1) * per])
         f = vals[len(vals) // 2] * 1024 * fetch_factor
-        lines.append("%-5s %-28s %3d %7.1f %10.1f %17.2f %12.0f" %
-                     (r["prec"], tuple(r["cfg"]), r["par"], t["us"], f / 1e6, (f - G) / S,
-                      f / (t["us"] * 1e-6) / 1e9))
+        lines.append("%-5s %3d %-28s %3d %7.1f %10.1f %17.2f %12.0f" %
+                     (r["prec"], r.get("variant", -1), tuple(r["cfg"]), r["par"], t["us"],
+                      f / 1e6, (f - G) / S, f / (t["us"] * 1e-6) / 1e9))
     with open(out_path, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     return out_path
