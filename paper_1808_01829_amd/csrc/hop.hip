@@ -510,7 +510,7 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_s(const cplx<T>* __restrict__ li
     const void* le[3] = {L + q * st,
                          mlane ? (const void*)(sgn + (kF64 ? (ps & ~3u) : ps))
                                : (const void*)(L + e1 * st),
-                         L + e2 * st};
+                         EPL == 9 ? L + e2 * st : L};
 #pragma unroll
     for (int e = 0; e < NLK; ++e) {
       if constexpr (kF64) {
@@ -584,27 +584,44 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_s(const cplx<T>* __restrict__ li
     const unsigned char* sp = ring + slot * SLOT;
     C v[3][R], lt[3];
     read_cols(sp, v);
+    lt[2] = lt[0];  // (a third entry only with nine-entry links)
     if constexpr (kF64) {
       d2v w[3];
-      asm volatile(
-          "ds_read_b128 %0, %3\n ds_read_b128 %1, %3 offset:1024\n"
-          "ds_read_b128 %2, %3 offset:2048\n s_waitcnt lgkmcnt(0)"
-          : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2])
-          : "v"(lds_addr(sp + IN + 16 * lane)));
-      // (the third word, past a two-row slot, lies in this wave's LDS and is unused)
+      const uint32_t lb = lds_addr(sp + IN + 16 * lane);
+      if constexpr (NLK == 3) {
+        asm volatile(
+            "ds_read_b128 %0, %3\n ds_read_b128 %1, %3 offset:1024\n"
+            "ds_read_b128 %2, %3 offset:2048\n s_waitcnt lgkmcnt(0)"
+            : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2])
+            : "v"(lb));
+      } else {
+        asm volatile("ds_read_b128 %0, %2\n ds_read_b128 %1, %2 offset:1024\n s_waitcnt lgkmcnt(0)"
+                     : "=&v"(w[0]), "=&v"(w[1])
+                     : "v"(lb));
+      }
 #pragma unroll
-      for (int e = 0; e < 3; ++e) lt[e] = make_double2(w[e].x, w[e].y);
+      for (int e = 0; e < NLK; ++e) lt[e] = make_double2(w[e].x, w[e].y);
     } else {
       float w[6];
-      asm volatile(
-          "ds_read_b32 %0, %6\n ds_read_b32 %1, %6 offset:256\n"
-          "ds_read_b32 %2, %6 offset:512\n ds_read_b32 %3, %6 offset:768\n"
-          "ds_read_b32 %4, %6 offset:1024\n ds_read_b32 %5, %6 offset:1280\n"
-          "s_waitcnt lgkmcnt(0)"
-          : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5])
-          : "v"(lds_addr(sp + IN + 4 * lane)));
+      const uint32_t lb = lds_addr(sp + IN + 4 * lane);
+      if constexpr (NLK == 3) {
+        asm volatile(
+            "ds_read_b32 %0, %6\n ds_read_b32 %1, %6 offset:256\n"
+            "ds_read_b32 %2, %6 offset:512\n ds_read_b32 %3, %6 offset:768\n"
+            "ds_read_b32 %4, %6 offset:1024\n ds_read_b32 %5, %6 offset:1280\n"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5])
+            : "v"(lb));
+      } else {
+        asm volatile(
+            "ds_read_b32 %0, %4\n ds_read_b32 %1, %4 offset:256\n"
+            "ds_read_b32 %2, %4 offset:512\n ds_read_b32 %3, %4 offset:768\n"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3])
+            : "v"(lb));
+      }
 #pragma unroll
-      for (int e = 0; e < 3; ++e) lt[e] = make_float2(w[2 * e], w[2 * e + 1]);
+      for (int e = 0; e < NLK; ++e) lt[e] = make_float2(w[2 * e], w[2 * e + 1]);
     }
     if (k == 0) {
       cs = group_site(i);
