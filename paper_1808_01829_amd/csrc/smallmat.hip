@@ -74,12 +74,14 @@ __device__ void sm_identity(double2* A, int n) {
 // the square root of the pivot, scales row j, and subtracts row j's outer
 // product from the trailing rows. Every entry sees the same operations in
 // the same order as the dot-product (left-looking) form, so the factor is
-// the same bit for bit, with no one-thread loops between the barriers.
+// the same bit for bit, with no one-thread loops between the barriers. Every
+// thread reads the pivot (the previous step's barrier made it final) and
+// takes the same decision, so a step needs two barriers: one after the row
+// is scaled, one after the trailing update (which does not read the pivot;
+// the square root replaces it there).
 __device__ int sm_chol_upper(double2* R, const double2* G, int n, double tol) {
-  __shared__ int status;
   __shared__ double trace;
   if (threadIdx.x == 0) {
-    status = 0;
     double tr = 0;
     for (int i = 0; i < n; ++i) tr += G[i * n + i].x;
     trace = tr;
@@ -89,18 +91,15 @@ __device__ int sm_chol_upper(double2* R, const double2* G, int n, double tol) {
     R[e] = l >= i ? G[e] : make_double2(0, 0);
   }
   __syncthreads();
+  const double tr = trace;
   for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = R[j * n + j].x;
-      if (!(d == d) || !(trace == trace) || !(fabs(trace) < 1e300)) status = BMS_ENAN;
-      else if (!(d > tol * trace)) status = BMS_EBREAKDOWN;
-      R[j * n + j] = make_double2(status ? 1.0 : sqrt(d), 0);
-    }
-    __syncthreads();
-    if (status) return status;
-    const double djj = R[j * n + j].x;
+    const double d = R[j * n + j].x;
+    if (!(d == d) || !(tr == tr) || !(fabs(tr) < 1e300)) return BMS_ENAN;
+    if (!(d > tol * tr)) return BMS_EBREAKDOWN;
+    const double djj = sqrt(d);
     for (int l = j + 1 + threadIdx.x; l < n; l += BMS_WG) R[j * n + l] = cdiv_real(R[j * n + l], djj);
     __syncthreads();
+    if (threadIdx.x == 0) R[j * n + j] = make_double2(djj, 0);
     const int m = n - j - 1;
     for (int e = threadIdx.x; e < m * m; e += BMS_WG) {
       const int i = j + 1 + e / m, l = j + 1 + (e - (e / m) * m);
@@ -131,6 +130,12 @@ __device__ void sm_triinv_upper(double2* X, const double2* R, int n) {
 
 // Ainv = A^-1 by Gauss-Jordan elimination with partial pivoting; A is
 // destroyed. Returns 0 or BMS_ENAN (singular / non-finite).
+// Column c: the pivot search, a row swap when the pivot is off the diagonal,
+// then in one phase the pivot row scaled and the multipliers (column c) read,
+// then the elimination, each phase ended by a barrier. The columns of A up
+// to c are not updated in step c: nothing reads them afterwards (the pivot
+// search and the multipliers use the columns beyond), so Ainv is the same
+// bit for bit as with every column updated.
 __device__ int sm_inv_general(double2* Ainv, double2* A, int n) {
   __shared__ int status;
   __shared__ int piv;
@@ -173,20 +178,20 @@ __device__ int sm_inv_general(double2* Ainv, double2* A, int n) {
       }
       __syncthreads();
     }
-    double2 inv = crecip(A[c * n + c]);
-    __syncthreads();
+    // the pivot itself is not written in this phase (column c of A is not
+    // updated), so every thread reads it
+    const double2 inv = crecip(A[c * n + c]);
     for (int k = threadIdx.x; k < n; k += BMS_WG) {
-      A[c * n + k] = cmul(A[c * n + k], inv);
+      if (k > c) A[c * n + k] = cmul(A[c * n + k], inv);
       Ainv[c * n + k] = cmul(Ainv[c * n + k], inv);
     }
-    __syncthreads();
     for (int r = threadIdx.x; r < n; r += BMS_WG) fac[r] = A[r * n + c];
     __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += BMS_WG) {
       int r = e / n, k = e - (e / n) * n;
       if (r == c) continue;
       double2 f = fac[r];
-      A[e] = csub(A[e], cmul(f, A[c * n + k]));
+      if (k > c) A[e] = csub(A[e], cmul(f, A[c * n + k]));
       Ainv[e] = csub(Ainv[e], cmul(f, Ainv[c * n + k]));
     }
     __syncthreads();
