@@ -56,3 +56,55 @@ def test_cpu_baseline_leg_on_a_small_workload():
     assert out["value"] > 0
     assert re.search(r"[0-9.]+ s/iteration", out["sample"])
     assert "scaled to the 500 iterations" in out["sample"]
+
+
+def test_hop_traversal_table(tmp_path):
+    """--write-hop-traversal: each row's fetch is the median FETCH_SIZE of its
+    timed launches (the untimed first one skipped) scaled by the copy
+    calibration, shown in MB and in block vectors beyond the links; a counter
+    run with another number of hop dispatches is refused."""
+    import csv as _csv
+    dims, n, reps = [4, 4, 4, 4], 16, 3
+    rows = [dict(prec="f64", variant=-1, cfg=[0, 0, 0, 2, 1], par=1),
+            dict(prec="f32", variant=4, cfg=[8, 8, 8, 4, 1], par=0)]
+    run = dict(lattice=dims, n=n, link_rows=2, reps=reps, rows=rows)
+    tim = dict(run, rows=[dict(r, us=10.0) for r in rows])
+    (tmp_path / "pmc.json").write_text("log line\n" + json.dumps(run) + "\n")
+    (tmp_path / "time.json").write_text(json.dumps(tim) + "\n")
+    vh = 4 ** 4 // 2
+
+    def sizes(b):
+        return vh * 3 * n * 2 * b, vh * 8 * 6 * 2 * b   # S, G
+
+    def write_csv(path, vals):
+        with open(path, "w", newline="") as f:
+            w = _csv.writer(f)
+            w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            for i, (k, v) in enumerate(vals):
+                w.writerow([i, k, "FETCH_SIZE", v])
+    # calibration: 1 GiB copy counted as 2^19 KiB (factor 2)
+    write_csv(tmp_path / "cal.csv", [("fill", 1.0), ("copy", 524288.0)])
+    S64, G64 = sizes(8)
+    S32, G32 = sizes(4)
+    # fetch = G + 2 S (FP64 row) and G + 3 S (FP32 row), in KiB before the factor 2
+    f64_kib = (G64 + 2 * S64) / 2048.0
+    f32_kib = (G32 + 3 * S32) / 2048.0
+    vals = [("k_hop_q", 1e9), ("k_hop_q", f64_kib), ("k_hop_q", f64_kib * 1.5), ("k_hop_q", f64_kib),
+            ("k_hop_s", 1e9), ("k_hop_s", f32_kib), ("k_hop_s", f32_kib), ("k_hop_s", 0.0)]
+    write_csv(tmp_path / "fetch.csv", vals + [("k_other", 5.0)])
+    out = bench.write_hop_traversal(str(tmp_path / "fetch.csv"), str(tmp_path / "pmc.json"),
+                                    str(tmp_path / "time.json"), str(tmp_path / "cal.csv"),
+                                    "cmd", str(tmp_path / "t.txt"))
+    lines = [l for l in open(out) if l.startswith(("f64", "f32"))]
+    assert len(lines) == 2
+    f = lines[0].split()
+    assert f[1] == "-1" and abs(float(f[-2]) - 2.0) < 1e-9
+    assert abs(float(f[-3]) - (G64 + 2 * S64) / 1e6) < 0.05
+    g = lines[1].split()
+    assert g[1] == "4" and abs(float(g[-2]) - 3.0) < 1e-9
+    write_csv(tmp_path / "fetch.csv", vals[:-1])
+    import pytest
+    with pytest.raises(SystemExit):
+        bench.write_hop_traversal(str(tmp_path / "fetch.csv"), str(tmp_path / "pmc.json"),
+                                  str(tmp_path / "time.json"), str(tmp_path / "cal.csv"),
+                                  "cmd", str(tmp_path / "t.txt"))
