@@ -345,23 +345,14 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[a3][r] = czero<C>();
   const size_t st = (size_t)1 << sbl;
-  // Per hop every load (three link elements, 3R input columns) is issued
-  // before any of them is used; the scheduling barrier keeps the scheduler
-  // from spreading them next to their uses, which leaves about two in flight.
-#pragma unroll 2
-  for (int k = 0; k < NL; ++k) {
-    const int mu = k & 3;
-    const int nb = neighbour_cb((int)s, c, g, mu, hop_dist(k));
-    const C* src = in + (size_t)nb * 3 * n + j0;
+  // hop k's link entries of this thread, and hop k's contribution to acc
+  auto link_load = [&](int k, C& t0, C& t1, C& t2) {
     const C* L = links + link_off(s, k, 0, sbl, EPL * NL, EPL);
-    const C t0 = link_ld<NT>(L + q * st), t1 = link_ld<NT>(L + e1 * st);
-    const C t2 = EPL == 9 ? link_ld<NT>(L + e2 * st) : t1;
-    C v[3][R];
-#pragma unroll
-    for (int cb = 0; cb < 3; ++cb)
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[cb][r] = src[cb * n + r * cstep];
-    __builtin_amdgcn_sched_barrier(0);
+    t0 = link_ld<NT>(L + q * st);
+    t1 = link_ld<NT>(L + e1 * st);
+    t2 = EPL == 9 ? link_ld<NT>(L + e2 * st) : t1;
+  };
+  auto accumulate = [&](int k, const C (&v)[3][R], C t0, C t1, C t2) {
     C l[9];
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
@@ -380,6 +371,56 @@ __global__ __launch_bounds__(BMS_WG) void k_hop_q(const cplx<T>* __restrict__ li
       for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[a3][r] = cfma(l[3 * a3 + cb], v[cb][r], acc[a3][r]);
+  };
+  auto col_load = [&](int nb, C (&v)[3][R]) {
+    const C* src = in + (size_t)nb * 3 * n + j0;
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[cb][r] = src[cb * n + r * cstep];
+  };
+  // The two x hops first. Along an x-row the -x neighbour of a site is the
+  // +x neighbour of the site before it (with the row's wrap, of the row's
+  // last site), so where the wave holds that site (four lanes down, the same
+  // q) the -x columns come from its +x columns by cross-lane moves instead of
+  // a second read from L2; the other lanes (first site of the wave, rows that
+  // do not fill the wave) load them.
+  {
+    const int lane = (int)(threadIdx.x & 63);
+    const bool full = blockIdx.x * BMS_WG + (threadIdx.x & ~63u) + 64 <= (uint32_t)g.vh * 4;
+    const int from = (lane - 4) & 63;
+    const int nb0 = neighbour_cb((int)s, c, g, 0, 1), nb4 = neighbour_cb((int)s, c, g, 0, -1);
+    C t0, t1, t2, v[3][R];
+    link_load(0, t0, t1, t2);
+    col_load(nb0, v);
+    __builtin_amdgcn_sched_barrier(0);
+    C u0, u1, u2, w[3][R];
+    link_load(4, u0, u1, u2);
+    const int there = __shfl(nb0, from);
+#pragma unroll
+    for (int cb = 0; cb < 3; ++cb)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        w[cb][r].x = __shfl(v[cb][r].x, from);
+        w[cb][r].y = __shfl(v[cb][r].y, from);
+      }
+    if (!((lane >= 4 || full) && there == nb4)) col_load(nb4, w);
+    accumulate(0, v, t0, t1, t2);
+    accumulate(4, w, u0, u1, u2);
+  }
+  // The other hops: every load of a hop (three link elements, 3R input
+  // columns) is issued before any of them is used; the scheduling barrier
+  // keeps the scheduler from spreading them next to their uses, which leaves
+  // about two in flight.
+#pragma unroll 2
+  for (int kk = 0; kk < NL - 2; ++kk) {
+    const int k = kk + (kk < 3 ? 1 : 2);
+    const int nb = neighbour_cb((int)s, c, g, k & 3, hop_dist(k));
+    C t0, t1, t2, v[3][R];
+    link_load(k, t0, t1, t2);
+    col_load(nb, v);
+    __builtin_amdgcn_sched_barrier(0);
+    accumulate(k, v, t0, t1, t2);
   }
   const size_t o = (size_t)s * 3 * n + j0;
 #pragma unroll
